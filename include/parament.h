@@ -1,0 +1,178 @@
+/*
+ * parament.h -- C ABI of the MI355X parallel-in-time Schrodinger propagator.
+ *
+ * The library computes the propagator of
+ *     i dU/dt = H(t) U,   H(t) = H0 + sum_k c_k(t) H_k         (hbar = 1)
+ * (eq. schroedinger with H = hbar * calH; control decomposition
+ * eq. format_control) over N equal slices of width h, following the pipeline
+ * of the Computational approach section (Fig. 1):
+ *   1. expand: one Hermitian exponent G_j per slice, by the midpoint rule
+ *      (order 2) or by 4th-order commutator Magnus with Simpson quadrature
+ *      (order 4, Magnus integrators section, eq. magnus_coeffs);
+ *   2. exponentiate all slices at once, U_j = exp(-i G_j), by scaling and
+ *      squaring with a truncated Taylor series (Matrix exponential section);
+ *   3. reduce U(T) = U_{N-1} ... U_1 U_0 (eq. slices) by chunked products and
+ *      a log-depth pairwise tree (Reduction by matrix multiplication section).
+ * The usage model is the state machine of the PARAMENT library section
+ * (Fig. state_machine): create a context, set the Hamiltonians once, then
+ * propagate any number of control sequences.
+ *
+ * Conventions for every entry point
+ *   - Complex arrays are interleaved (re, im) pairs of double (complex128) or
+ *     float (complex64), row-major: element (r, c) of a d x d matrix is at
+ *     pair index r*d + c.  Matrix stacks are [n][d][d].
+ *   - Control samples are float64, laid out [n_ctrl][n_samples] (control k
+ *     contiguous).  Order 2: n_samples = N, sample j is H's control value at
+ *     the slice midpoint (j + 1/2) h.  Order 4: n_samples = 2N + 1 (odd,
+ *     >= 3), sample i at t = i h / 2; slice j uses samples 2j, 2j+1, 2j+2.
+ *   - dt is the slice width h for both orders (for order 4 the paper's
+ *     sample spacing is h/2).
+ *   - Product order: later slices multiply from the left.
+ *   - The caller owns every buffer passed in.  pm_set_hamiltonian copies its
+ *     inputs; they persist across propagations until replaced.
+ *   - Errors are reported only through pm_status; no exception or abort
+ *     crosses the ABI.  On error, outputs are left untouched and the context
+ *     stays usable, except after PM_E_DEVICE.  pm_last_error() describes the
+ *     most recent failure on a context.
+ *   - A context is neither thread-safe nor reentrant; distinct contexts are
+ *     independent (PARAMENT library section).
+ */
+#ifndef PARAMENT_H
+#define PARAMENT_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef struct pm_ctx pm_ctx;
+
+typedef enum pm_status {
+    PM_OK = 0,
+    PM_E_INVALID_ARG = 1,   /* bad size, order, pointer or sample count      */
+    PM_E_NOT_READY = 2,     /* propagation before pm_set_hamiltonian         */
+    PM_E_NOT_HERMITIAN = 3, /* max|H - H^H| > 1e-12 * max(1, max|H|)        */
+    PM_E_OOM = 4,           /* device or host allocation failed              */
+    PM_E_DEVICE = 5,        /* HIP runtime error; the context is unusable    */
+    PM_E_UNSUPPORTED = 6    /* dimension or mode not built into this library */
+} pm_status;
+
+/* Arithmetic of the exponentiate and reduce steps.  Planning (norms, choice
+ * of Taylor degree and scaling exponent) is FP64 in every mode. */
+typedef enum pm_precision {
+    PM_FP64 = 0,       /* complex128 throughout                                */
+    PM_FP32 = 1,       /* complex64 products (4 real FP32 products each);
+                          squarings and the tree above the chunks in FP64      */
+    PM_FP32_3M = 2,    /* complex64 with 3-real-product complex multiplication;
+                          squarings and tree top in FP64                       */
+    PM_BF16_SPLIT = 3  /* 3M products on BF16 hi/lo split operands with FP32
+                          accumulation; squarings and tree top in FP64         */
+} pm_precision;
+
+/* Largest dimension served.  Dimensions that are not a power of two are
+ * embedded (zero-padded) in the next supported size. */
+#define PM_MAX_DIM 64
+/* Largest Taylor degree the planner may choose. */
+#define PM_MAX_TAYLOR_DEGREE 21
+
+/* Create a context on HIP device `device` computing in `precision`.
+ * *out receives the handle (NULL on failure).  Allocates nothing on the
+ * device until pm_set_hamiltonian. */
+pm_status pm_create(pm_ctx **out, int device, int precision);
+
+/* Release a context and every device buffer it owns.  NULL is accepted. */
+pm_status pm_destroy(pm_ctx *ctx);
+
+/* Upload the drift H0 [dim][dim] and controls Hk [n_ctrl][dim][dim]
+ * (complex128, Hermitian; Hk may be NULL when n_ctrl == 0) and choose the
+ * integrator order (2: midpoint rule; 4: commutator Magnus).  For order 4 the
+ * host forms the effective control Hamiltonians of eq. magnus_coeffs,
+ * i[H0,H_k] and i[H_k,H_k'] (k<k'), all Hermitian, and uploads them too
+ * (setHamiltonian of the PARAMENT library section).  Inputs are symmetrised
+ * to exact Hermiticity after the check.  1 <= dim <= PM_MAX_DIM,
+ * 0 <= n_ctrl <= 8. */
+pm_status pm_set_hamiltonian(pm_ctx *ctx, int64_t dim, const double *H0,
+                             int64_t n_ctrl, const double *Hk, int order);
+
+/* Propagate with host buffers (equiprop of the PARAMENT library section).
+ * samples: host [n_ctrl][n_samples] float64.  U_out: host [dim][dim]
+ * complex128, receives U(T).  slices_out: NULL, or host [N][dim][dim]
+ * receiving every U_j, complex128 for PM_FP64 and complex64 otherwise.
+ * Synchronous. */
+pm_status pm_equiprop(pm_ctx *ctx, const double *samples, int64_t n_samples,
+                      double dt, double *U_out, void *slices_out);
+
+/* Same with device buffers, enqueued on `stream` (a hipStream_t; NULL = the
+ * null stream) without synchronising.  samples_dev: device float64
+ * [n_ctrl][n_samples]; U_out_dev: device complex128 [dim][dim];
+ * slices_out_dev: NULL or device [N][dim][dim] (complex128 for PM_FP64,
+ * complex64 otherwise).  Buffers must stay valid until the stream reaches
+ * the end of this call's work.  The context's workspace is reused by the
+ * next call on the context, so calls on one context must be ordered on one
+ * stream. */
+pm_status pm_equiprop_dev(pm_ctx *ctx, const double *samples_dev,
+                          int64_t n_samples, double dt, double *U_out_dev,
+                          void *slices_out_dev, void *stream);
+
+/* Numerics helpers (PARAMENT library section: e.g. a different maximum
+ * degree).  max_taylor_degree in [1, PM_MAX_TAYLOR_DEGREE] caps the degree
+ * the planner may pick (default PM_MAX_TAYLOR_DEGREE); force_s >= 0 fixes the
+ * number of squarings for every slice (the degree is then the smallest that
+ * meets the precision's threshold, or the cap), -1 restores automatic choice.
+ * chunk > 0 fixes how many consecutive slices one wave team multiplies before
+ * the tree, 0 restores the automatic choice. */
+pm_status pm_set_expm_policy(pm_ctx *ctx, int max_taylor_degree, int force_s);
+pm_status pm_set_chunk(pm_ctx *ctx, int64_t chunk);
+
+/* Human-readable name of a status code (static storage). */
+const char *pm_status_string(pm_status s);
+
+/* Description of the most recent failure on ctx ("" if none; static storage
+ * owned by the context, valid until the next call on it). */
+const char *pm_last_error(const pm_ctx *ctx);
+
+/* ---- host-only helpers: no GPU is touched ------------------------------ */
+
+/* Number of Hermitian basis matrices: 1 + n_ctrl (order 2), or
+ * 1 + 2 n_ctrl + n_ctrl (n_ctrl - 1) / 2 (order 4, eq. magnus_coeffs:
+ * 3K/2 + K^2/2 effective controls besides H0).  -1 on bad arguments. */
+int64_t pm_basis_count(int64_t n_ctrl, int order);
+
+/* The basis the device receives, in FP64: basis_out [M][dim][dim]
+ * complex128 in the order H0, H_1..H_K, then for order 4 i[H0,H_k]
+ * (k = 1..K), then i[H_k,H_k'] for k < k' in lexicographic order;
+ * norms_out [M] their 1-norms (max column sum of |entries|).  Either output
+ * may be NULL. */
+pm_status pm_build_basis_host(int64_t dim, const double *H0, int64_t n_ctrl,
+                              const double *Hk, int order, double *basis_out,
+                              double *norms_out);
+
+/* Real weights w_{j,m} of slice j on that basis (the expand step):
+ * order 2: w = h (1, c_1[j], ..., c_K[j]);
+ * order 4 with s0, s1, s2 = samples 2j, 2j+1, 2j+2:
+ *   w_H0 = h, w_Hk = (h/6)(s0_k + 4 s1_k + s2_k),
+ *   w_i[H0,Hk] = (h^2/12)(s2_k - s0_k),
+ *   w_i[Hk,Hk'] = (h^2/12)(s0_k s2_k' - s2_k s0_k').
+ * weights_out [M]. */
+pm_status pm_slice_weights_host(int64_t n_ctrl, const double *samples,
+                                int64_t n_samples, double dt, int order,
+                                int64_t slice, double *weights_out);
+
+/* Truncation threshold theta_m of the degree-m Taylor polynomial for the
+ * precision's unit roundoff u (2^-53 FP64, 2^-24 FP32 modes, 2^-16 BF16
+ * split): the largest theta with theta^(m+1)/(m+1)! / (1 - theta/(m+2)) <= u,
+ * which bounds the remainder of exp(X) - T_m(X) for ||X|| <= theta. */
+pm_status pm_taylor_theta(int m, int precision, double *theta_out);
+
+/* The planner's choice for a slice with ||G||_1 = nu: Taylor degree m and
+ * squarings s minimising the product count (ties to the smaller s), subject
+ * to nu / 2^s <= theta_m and m <= max_degree. */
+pm_status pm_plan_expm(double nu, int precision, int max_degree, int *m_out,
+                       int *s_out);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* PARAMENT_H */

@@ -1,0 +1,228 @@
+"""Python binding of the MI355X parallel-in-time Schrodinger propagator.
+
+Argument marshalling only: every step of the propagation runs in the HIP
+library ``libparament.so`` (built in-tree by ``paper_2108_07126_amd.build``),
+reached through its C ABI (include/parament.h) with ctypes.  Importing this
+package fails loudly when the library has not been built; there is no other
+code path.
+
+PyTorch is used only for device memory and streams (``equiprop_dev`` takes
+CUDA/HIP tensors and enqueues on torch's current stream).
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+from typing import Optional, Tuple
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libparament.so")
+
+PM_FP64, PM_FP32, PM_FP32_3M, PM_BF16_SPLIT = 0, 1, 2, 3
+PRECISIONS = {"fp64": PM_FP64, "fp32": PM_FP32, "fp32_3m": PM_FP32_3M, "bf16_split": PM_BF16_SPLIT}
+STATUS = ["PM_OK", "PM_E_INVALID_ARG", "PM_E_NOT_READY", "PM_E_NOT_HERMITIAN", "PM_E_OOM",
+          "PM_E_DEVICE", "PM_E_UNSUPPORTED"]
+MAX_DIM = 64
+MAX_TAYLOR_DEGREE = 21
+
+_c_double_p = ctypes.POINTER(ctypes.c_double)
+_c_int_p = ctypes.POINTER(ctypes.c_int)
+
+# name -> (restype, argtypes): every entry point declared in include/parament.h
+SIGNATURES = {
+    "pm_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int]),
+    "pm_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pm_set_hamiltonian": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                          ctypes.c_int64, ctypes.c_void_p, ctypes.c_int]),
+    "pm_equiprop": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                   ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_equiprop_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_set_expm_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
+    "pm_set_chunk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "pm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
+    "pm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "pm_basis_count": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int]),
+    "pm_build_basis_host": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                           ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_slice_weights_host": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                             ctypes.c_int, ctypes.c_int64, ctypes.c_void_p]),
+    "pm_taylor_theta": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_double_p]),
+    "pm_plan_expm": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int, _c_int_p, _c_int_p]),
+}
+
+
+def _load():
+    if not os.path.exists(LIB_PATH):
+        raise ImportError(
+            f"{LIB_PATH} is missing: build the HIP library first "
+            "(python -m paper_2108_07126_amd.build)")
+    lib = ctypes.CDLL(LIB_PATH)
+    for name, (res, args) in SIGNATURES.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    return lib
+
+
+_lib = _load()
+
+
+class ParamentError(RuntimeError):
+    def __init__(self, status: int, detail: str = ""):
+        self.status = status
+        self.name = STATUS[status] if 0 <= status < len(STATUS) else f"status {status}"
+        super().__init__(f"{self.name}: {detail}" if detail else self.name)
+
+
+def _check(status: int, ctx=None):
+    if status != 0:
+        detail = _lib.pm_last_error(ctx).decode() if ctx else ""
+        raise ParamentError(status, detail)
+
+
+def _ptr(a: np.ndarray):
+    return a.ctypes.data_as(ctypes.c_void_p)
+
+
+def _as_c128(a) -> np.ndarray:
+    return np.ascontiguousarray(np.asarray(a, dtype=np.complex128))
+
+
+# ----------------------------------------------------------- host helpers
+
+def basis_count(n_ctrl: int, order: int) -> int:
+    return int(_lib.pm_basis_count(n_ctrl, order))
+
+
+def build_basis_host(H0, Hk, order: int) -> Tuple[np.ndarray, np.ndarray]:
+    """The Hermitian basis the device receives (FP64) and its 1-norms."""
+    H0 = _as_c128(H0)
+    d = H0.shape[0]
+    Hk = _as_c128(Hk).reshape(-1, d, d)
+    K = Hk.shape[0]
+    M = basis_count(K, order)
+    if M < 0:
+        raise ParamentError(1, "bad n_ctrl / order")
+    out = np.zeros((M, d, d), np.complex128)
+    norms = np.zeros(M)
+    _check(_lib.pm_build_basis_host(d, _ptr(H0), K, _ptr(Hk) if K else None, order, _ptr(out), _ptr(norms)))
+    return out, norms
+
+
+def slice_weights_host(samples, dt: float, order: int, slice_index: int) -> np.ndarray:
+    s = np.ascontiguousarray(np.asarray(samples, np.float64))
+    K, S = s.shape
+    w = np.zeros(basis_count(K, order))
+    _check(_lib.pm_slice_weights_host(K, _ptr(s) if K else None, S, dt, order, slice_index, _ptr(w)))
+    return w
+
+
+def taylor_theta(m: int, precision: int = PM_FP64) -> float:
+    t = ctypes.c_double()
+    _check(_lib.pm_taylor_theta(m, precision, ctypes.byref(t)))
+    return t.value
+
+
+def plan_expm(nu: float, precision: int = PM_FP64, max_degree: int = MAX_TAYLOR_DEGREE) -> Tuple[int, int]:
+    m, s = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.pm_plan_expm(nu, precision, max_degree, ctypes.byref(m), ctypes.byref(s)))
+    return m.value, s.value
+
+
+def n_slices(n_samples: int, order: int) -> int:
+    return n_samples if order == 2 else (n_samples - 1) // 2
+
+
+# ------------------------------------------------------------------ context
+
+class Context:
+    """A propagator context (create -> set_hamiltonian -> equiprop ...)."""
+
+    def __init__(self, device: int = 0, precision: int = PM_FP64):
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        h = ctypes.c_void_p()
+        _check(_lib.pm_create(ctypes.byref(h), device, precision))
+        self._h = h
+        self.precision = precision
+        self.dim = None
+        self.n_ctrl = None
+        self.order = None
+
+    @property
+    def handle(self):
+        return self._h
+
+    def close(self):
+        if self._h:
+            _lib.pm_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_hamiltonian(self, H0, Hk, order: int = 2):
+        H0 = _as_c128(H0)
+        d = H0.shape[0]
+        Hk = _as_c128(Hk).reshape(-1, d, d)
+        K = Hk.shape[0]
+        _check(_lib.pm_set_hamiltonian(self._h, d, _ptr(H0), K, _ptr(Hk) if K else None, order), self._h)
+        self.dim, self.n_ctrl, self.order = d, K, order
+
+    def set_expm_policy(self, max_taylor_degree: int = MAX_TAYLOR_DEGREE, force_s: int = -1):
+        _check(_lib.pm_set_expm_policy(self._h, max_taylor_degree, force_s), self._h)
+
+    def set_chunk(self, chunk: int = 0):
+        _check(_lib.pm_set_chunk(self._h, chunk), self._h)
+
+    def equiprop(self, samples, dt: float, return_slices: bool = False):
+        """U(T) (complex128) from host samples [n_ctrl][n_samples]; optionally all U_j."""
+        s = np.ascontiguousarray(np.asarray(samples, np.float64))
+        if s.ndim == 1:
+            s = s[None]
+        S = s.shape[1]
+        U = np.zeros((self.dim, self.dim), np.complex128)
+        sl = None
+        if return_slices:
+            dt_c = np.complex128 if self.precision == PM_FP64 else np.complex64
+            sl = np.zeros((n_slices(S, self.order), self.dim, self.dim), dt_c)
+        _check(_lib.pm_equiprop(self._h, _ptr(s), S, float(dt), _ptr(U), _ptr(sl) if sl is not None else None),
+               self._h)
+        return (U, sl) if return_slices else U
+
+    def equiprop_dev(self, samples_t, dt: float, U_t, slices_t=None, stream=None):
+        """Device variant: torch tensors on the GPU; enqueued on `stream`
+        (default: torch's current stream), not synchronised."""
+        import torch
+        assert samples_t.is_cuda and samples_t.dtype == torch.float64 and samples_t.is_contiguous()
+        assert U_t.is_cuda and U_t.dtype == torch.complex128 and U_t.is_contiguous()
+        if slices_t is not None:
+            want = torch.complex128 if self.precision == PM_FP64 else torch.complex64
+            assert slices_t.is_cuda and slices_t.dtype == want and slices_t.is_contiguous()
+        if stream is None:
+            stream = torch.cuda.current_stream(U_t.device)
+        S = samples_t.shape[-1]
+        _check(_lib.pm_equiprop_dev(self._h, ctypes.c_void_p(samples_t.data_ptr()), S, float(dt),
+                                    ctypes.c_void_p(U_t.data_ptr()),
+                                    ctypes.c_void_p(slices_t.data_ptr()) if slices_t is not None else None,
+                                    ctypes.c_void_p(stream.cuda_stream)), self._h)
+
+
+def propagate(H0, Hk, samples, dt: float, order: int = 2, precision: int = PM_FP64,
+              return_slices: bool = False, device: int = 0):
+    """One-shot helper: create a context, set the Hamiltonian, propagate."""
+    with Context(device, precision) as ctx:
+        ctx.set_hamiltonian(H0, Hk, order)
+        return ctx.equiprop(samples, dt, return_slices)

@@ -1,0 +1,452 @@
+// MFMA engine for dimensions 16, 32 and 64 (and smaller ones embedded in 16).
+//
+// One *team* of (D/16)^2 wavefronts runs a chain of consecutive slices; each
+// wave owns one 16x16 output tile of every D x D matrix, held in registers in
+// the accumulator layout of v_mfma_*_16x16x4 (lane 16 g + j holds rows
+// 4 g + r, r = 0..3, of column j).  Per slice the team
+//   1. expands G_j = sum_m w_m B_m in FP64 (weights from the control samples,
+//      basis tiles streamed from HBM/L2 in that same layout),
+//   2. takes ||G_j||_1 in FP64 and plans the Taylor degree m and squarings s,
+//   3. evaluates exp(-i G) = C(Y) - i G S'(Y), Y = G^2 (cos / sin Taylor
+//      series split by parity: every product is of commuting Hermitian
+//      matrices), then squares s times,
+//   4. optionally stores U_j, and multiplies it into the team's chain
+//      product Q <- U_j Q (later slices on the left, eq. slices).
+// Operands of each complex product are staged in LDS (row stride D+1, split
+// re/im planes, conflict-free fragment reads) and multiplied as four real
+// products on MFMA (FP64: v_mfma_f64_16x16x4f64; FP32: v_mfma_f32_16x16x4f32).
+// Finally the chain products are reduced by a pairwise tree in FP64 whose
+// nodes meet through per-pair tickets: the second team to finish a pair
+// multiplies it (odd leftovers are carried up unchanged) -- the reduction of
+// the Reduction by matrix multiplication section, in one launch.
+#include <type_traits>
+
+#include "engine_common.h"
+
+namespace pm {
+namespace {
+
+typedef double d4_t __attribute__((ext_vector_type(4)));
+typedef float f4_t __attribute__((ext_vector_type(4)));
+
+template <typename T> struct V4;
+template <> struct V4<double> { using type = d4_t; };
+template <> struct V4<float> { using type = f4_t; };
+
+__device__ __forceinline__ d4_t mfma16(double a, double b, d4_t c) {
+    return __builtin_amdgcn_mfma_f64_16x16x4f64(a, b, c, 0, 0, 0);
+}
+__device__ __forceinline__ f4_t mfma16(float a, float b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x4f32(a, b, c, 0, 0, 0);
+}
+
+template <typename T>
+struct Tile {
+    T re[4], im[4];
+};
+
+// Row (within a 16x16 tile) of accumulator register r in lane group g.  The
+// FP32 16x16x4 product leaves rows 4g..4g+3 in a lane; the FP64 one
+// interleaves them as g, g+4, g+8, g+12.  Column = lane & 15 for both.
+template <typename T> __device__ __forceinline__ int crow(int g, int r);
+template <> __device__ __forceinline__ int crow<double>(int g, int r) { return g + 4 * r; }
+template <> __device__ __forceinline__ int crow<float>(int g, int r) { return 4 * g + r; }
+
+template <int D_, int NT_>
+struct Geo {
+    static constexpr int D = D_;
+    static constexpr int TD = D / 16;
+    static constexpr int TW = TD * TD;   // waves per team
+    static constexpr int NT = NT_;       // teams per block
+    static constexpr int THREADS = 64 * TW * NT;
+    static constexpr int LD = D + 1;     // padded LDS row stride
+    static constexpr int PLANE = D * LD;
+    static constexpr int SLOT = 2 * PLANE;   // in doubles (a float slot uses the front half)
+    static_assert(TW == 1 || NT == 1, "multi-wave teams own their whole block");
+};
+
+// Per-wave coordinates.
+struct Lane {
+    int lane, g, j, TI, TJ, wt;
+};
+
+template <class G>
+__device__ __forceinline__ void team_sync() {
+    if constexpr (G::TW == 1) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    } else {
+        __syncthreads();
+    }
+}
+
+template <typename T>
+__device__ __forceinline__ Tile<T> ident(const Lane& L) {
+    Tile<T> t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        t.re[r] = (16 * L.TI + crow<T>(L.g, r) == 16 * L.TJ + L.j) ? T(1) : T(0);
+        t.im[r] = T(0);
+    }
+    return t;
+}
+
+template <typename T>
+__device__ __forceinline__ void axpy(Tile<T>& y, double a, const Tile<T>& x) {
+    const T ta = (T)a;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        y.re[r] += ta * x.re[r];
+        y.im[r] += ta * x.im[r];
+    }
+}
+
+template <class G, typename T>
+__device__ __forceinline__ void slot_store(double* slot, const Tile<T>& t, const Lane& L) {
+    T* re = reinterpret_cast<T*>(slot);
+    T* im = re + G::PLANE;
+    const int col = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<T>(L.g, r);
+        re[row * G::LD + col] = t.re[r];
+        im[row * G::LD + col] = t.im[r];
+    }
+}
+
+// Change a tile's element type; the register layouts differ between FP32
+// and FP64 accumulators, so the values travel through an LDS slot.
+template <class G, typename Tdst, typename Tsrc>
+__device__ __forceinline__ Tile<Tdst> relayout(const Tile<Tsrc>& t, double* slot, const Lane& L) {
+    if constexpr (std::is_same<Tdst, Tsrc>::value) {
+        return t;
+    } else {
+        team_sync<G>();
+        slot_store<G, Tsrc>(slot, t, L);
+        team_sync<G>();
+        const Tsrc* re = reinterpret_cast<const Tsrc*>(slot);
+        const Tsrc* im = re + G::PLANE;
+        const int col = 16 * L.TJ + L.j;
+        Tile<Tdst> o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * L.TI + crow<Tdst>(L.g, r);
+            o.re[r] = (Tdst)re[row * G::LD + col];
+            o.im[r] = (Tdst)im[row * G::LD + col];
+        }
+        return o;
+    }
+}
+
+// Tile (TI, TJ) of A * B, A and B complex D x D in LDS slots.
+template <class G, typename T>
+__device__ __forceinline__ Tile<T> slot_mul(const double* A, const double* B, const Lane& L) {
+    using V = typename V4<T>::type;
+    const T* Are = reinterpret_cast<const T*>(A);
+    const T* Aim = Are + G::PLANE;
+    const T* Bre = reinterpret_cast<const T*>(B);
+    const T* Bim = Bre + G::PLANE;
+    V rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
+    const int arow = (16 * L.TI + L.j) * G::LD;
+    const int bcol = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int kb = 0; kb < G::D / 4; ++kb) {
+        const int k = 4 * kb + L.g;
+        const T ar = Are[arow + k], ai = Aim[arow + k];
+        const T br = Bre[k * G::LD + bcol], bi = Bim[k * G::LD + bcol];
+        rr = mfma16(ar, br, rr);
+        ii = mfma16(ai, bi, ii);
+        ri = mfma16(ar, bi, ri);
+        ir = mfma16(ai, br, ir);
+    }
+    Tile<T> out;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out.re[r] = rr[r] - ii[r];
+        out.im[r] = ri[r] + ir[r];
+    }
+    return out;
+}
+
+// ||G||_1 (max over columns of sum_i |G_ij|), FP64, same value in every lane.
+template <class G>
+__device__ __forceinline__ double team_norm1(const double* gre, const double* gim, const Lane& L,
+                                             double* red) {
+    double cs = 0.0;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) cs += sqrt(gre[r] * gre[r] + gim[r] * gim[r]);
+    cs += __shfl_xor(cs, 16);
+    cs += __shfl_xor(cs, 32);
+    double mx;
+    if constexpr (G::TW == 1) {
+        mx = cs;
+    } else {
+        if (L.lane < 16) red[L.TI * G::D + 16 * L.TJ + L.lane] = cs;
+        __syncthreads();
+        mx = 0.0;
+        if (L.lane < G::D) {
+#pragma unroll
+            for (int ti = 0; ti < G::TD; ++ti) mx += red[ti * G::D + L.lane];
+        }
+        __syncthreads();
+    }
+#pragma unroll
+    for (int off = 1; off < 64; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off));
+    return mx;
+}
+
+// exp(-i G) for a (pre-scaled) Hermitian tile set by the degree-m Taylor
+// polynomial, split as C(Y) - i G S'(Y).  Uses slots s0, s1.
+template <class G, typename T>
+__device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s0, double* s1) {
+    Tile<T> C = ident<T>(L);
+    Tile<T> S;
+    if (m <= 1) {
+        S = Gt;
+    } else {
+        const int qc = m / 2;        // highest power of Y in C
+        const int qs = (m - 1) / 2;  // highest power of Y in S'
+        team_sync<G>();
+        slot_store<G, T>(s0, Gt, L);
+        team_sync<G>();
+        Tile<T> P = slot_mul<G, T>(s0, s0, L);   // Y = G G
+        Tile<T> Sp = ident<T>(L);
+        axpy(C, cos_coef(1), P);
+        if (qs >= 1) axpy(Sp, sin_coef(1), P);
+        if (qc >= 2) {
+            team_sync<G>();
+            slot_store<G, T>(s1, P, L);   // Y stays in s1
+            team_sync<G>();
+            for (int k = 2; k <= qc; ++k) {
+                if (k == 2) {
+                    P = slot_mul<G, T>(s1, s1, L);
+                } else {
+                    team_sync<G>();
+                    slot_store<G, T>(s0, P, L);
+                    team_sync<G>();
+                    P = slot_mul<G, T>(s0, s1, L);
+                }
+                axpy(C, cos_coef(k), P);
+                if (k <= qs) axpy(Sp, sin_coef(k), P);
+            }
+        }
+        if (qs >= 1) {
+            team_sync<G>();
+            slot_store<G, T>(s0, Gt, L);
+            slot_store<G, T>(s1, Sp, L);
+            team_sync<G>();
+            S = slot_mul<G, T>(s0, s1, L);
+        } else {
+            S = Gt;
+        }
+    }
+    Tile<T> U;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        U.re[r] = C.re[r] + S.im[r];
+        U.im[r] = C.im[r] - S.re[r];
+    }
+    return U;
+}
+
+template <class G, typename T>
+__device__ __forceinline__ Tile<T> square_n(Tile<T> U, int s, const Lane& L, double* s0) {
+    for (int i = 0; i < s; ++i) {
+        team_sync<G>();
+        slot_store<G, T>(s0, U, L);
+        team_sync<G>();
+        U = slot_mul<G, T>(s0, s0, L);
+    }
+    return U;
+}
+
+template <class G, typename T>
+__device__ __forceinline__ void store_slice(const PropParams& p, int64_t j, const Tile<T>& U,
+                                            const Lane& L) {
+    T* out = reinterpret_cast<T*>(p.slices_out) + j * (int64_t)p.du * p.du * 2;
+    const int col = 16 * L.TJ + L.j;
+    if (col >= p.du) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<T>(L.g, r);
+        if (row < p.du) {
+            out[(row * p.du + col) * 2 + 0] = U.re[r];
+            out[(row * p.du + col) * 2 + 1] = U.im[r];
+        }
+    }
+}
+
+template <class G>
+__device__ __forceinline__ void node_store(double* node, const Tile<double>& t, const Lane& L) {
+    const int col = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        node[(row * G::D + col) * 2 + 0] = t.re[r];
+        node[(row * G::D + col) * 2 + 1] = t.im[r];
+    }
+}
+
+template <class G>
+__device__ __forceinline__ Tile<double> node_load(const double* node, const Lane& L) {
+    Tile<double> t;
+    const int col = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        t.re[r] = node[(row * G::D + col) * 2 + 0];
+        t.im[r] = node[(row * G::D + col) * 2 + 1];
+    }
+    return t;
+}
+
+// Pairwise product tree over the chain products (FP64).  Level l holds
+// cnt_l nodes; node i pairs with i^1 (odd index = later slices = left
+// factor); an unpaired last node moves up unchanged.  The first team to reach
+// a pair leaves its product in `nodes` and exits; the second multiplies.
+template <class G>
+__device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
+                            double* s0, double* s1, int* tick) {
+    const int64_t NN = (int64_t)G::D * G::D * 2;
+    int64_t idx = leaf, cnt = p.n_leaves, off = 0;
+    while (cnt > 1) {
+        const int64_t pcnt = (cnt + 1) >> 1, poff = off + cnt, par = idx >> 1;
+        const bool carry = (idx == cnt - 1) && (cnt & 1);
+        if (!carry) {
+            node_store<G>(p.nodes + (off + idx) * NN, Q, L);
+            __threadfence();
+            unsigned t;
+            if constexpr (G::TW == 1) {
+                unsigned v = 0;
+                if (L.lane == 0) v = atomicAdd(&p.counters[poff + par], 1u);
+                t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(v, 0));
+            } else {
+                __syncthreads();
+                if (threadIdx.x == 0) *tick = (int)atomicAdd(&p.counters[poff + par], 1u);
+                __syncthreads();
+                t = (unsigned)*tick;
+                __syncthreads();
+            }
+            if (t == 0) return;
+            __threadfence();
+            if (L.lane == 0 && L.wt == 0) atomicExch(&p.counters[poff + par], 0u);
+            const Tile<double> other = node_load<G>(p.nodes + (off + (idx ^ 1)) * NN, L);
+            team_sync<G>();
+            slot_store<G, double>(s0, (idx & 1) ? Q : other, L);   // left factor: later slices
+            slot_store<G, double>(s1, (idx & 1) ? other : Q, L);
+            team_sync<G>();
+            Q = slot_mul<G, double>(s0, s1, L);
+        }
+        idx = par;
+        off = poff;
+        cnt = pcnt;
+    }
+    const int col = 16 * L.TJ + L.j;
+    if (col < p.du) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * L.TI + crow<double>(L.g, r);
+            if (row < p.du) {
+                p.U_out[(row * p.du + col) * 2 + 0] = Q.re[r];
+                p.U_out[(row * p.du + col) * 2 + 1] = Q.im[r];
+            }
+        }
+    }
+}
+
+template <typename T, int D, int NT>
+__global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
+propagate_mfma(PropParams p) {
+    using G = Geo<D, NT>;
+    __shared__ double smem[NT * 2 * G::SLOT];
+    __shared__ double red[G::TD * D];
+    __shared__ int tick;
+
+    Lane L;
+    L.lane = threadIdx.x & 63;
+    L.g = L.lane >> 4;
+    L.j = L.lane & 15;
+    const int wave = wave_uniform((int)(threadIdx.x >> 6));
+    const int team = wave / G::TW;
+    L.wt = wave % G::TW;
+    L.TI = L.wt / G::TD;
+    L.TJ = L.wt % G::TD;
+    const int64_t leaf = (int64_t)blockIdx.x * NT + team;
+    if (leaf >= p.n_leaves) return;
+    double* s0 = smem + team * 2 * G::SLOT;
+    double* s1 = s0 + G::SLOT;
+
+    const int64_t j0 = leaf * p.chunk;
+    const int64_t j1 = min(p.n_slices, j0 + p.chunk);
+    Tile<T> Q = ident<T>(L);
+    for (int64_t j = j0; j < j1; ++j) {
+        // expand (FP64)
+        double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
+        for (int m = 0; m < p.M; ++m) {
+            const double w = slice_weight(p, j, m);
+            const double* b = p.basis + mfma_basis_index(D, m, L.TI, L.TJ, 0, 0, L.lane);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                gre[r] = fma(w, b[r * 64], gre[r]);
+                gim[r] = fma(w, b[256 + r * 64], gim[r]);
+            }
+        }
+        // plan (FP64)
+        const double nu = wave_uniform(team_norm1<G>(gre, gim, L, red));
+        int m, s;
+        plan_expm(p, nu, m, s);
+        m = wave_uniform(m);
+        s = wave_uniform(s);
+        Tile<T> Gt;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Gt.re[r] = (T)ldexp(gre[r], -s);
+            Gt.im[r] = (T)ldexp(gim[r], -s);
+        }
+        // exponentiate
+        Tile<T> U = taylor_exp<G, T>(Gt, m, L, s0, s1);
+        if (s > 0) {
+            if constexpr (std::is_same<T, double>::value) {
+                U = square_n<G, double>(U, s, L, s0);
+            } else {
+                U = relayout<G, T>(square_n<G, double>(relayout<G, double>(U, s0, L), s, L, s0), s0, L);
+            }
+        }
+        if (p.slices_out) store_slice<G, T>(p, j, U, L);
+        // chain product Q <- U Q
+        team_sync<G>();
+        slot_store<G, T>(s0, U, L);
+        slot_store<G, T>(s1, Q, L);
+        team_sync<G>();
+        Q = slot_mul<G, T>(s0, s1, L);
+    }
+    tree_reduce<G>(p, leaf, relayout<G, double>(Q, s0, L), L, s0, s1, &tick);
+}
+
+template <typename T, int D, int NT>
+hipError_t launch_one(const PropParams& p, hipStream_t stream) {
+    using G = Geo<D, NT>;
+    const int64_t blocks = (p.n_leaves + NT - 1) / NT;
+    hipLaunchKernelGGL((propagate_mfma<T, D, NT>), dim3((unsigned)blocks), dim3(G::THREADS), 0,
+                       stream, p);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+// Teams per block for the one-wave teams of D = 16.
+constexpr int kNT16 = 4;
+
+hipError_t launch_mfma(int D, bool fp64, const PropParams& p, hipStream_t stream) {
+    switch (D) {
+        case 16: return fp64 ? launch_one<double, 16, kNT16>(p, stream) : launch_one<float, 16, kNT16>(p, stream);
+        case 32: return fp64 ? launch_one<double, 32, 1>(p, stream) : launch_one<float, 32, 1>(p, stream);
+        case 64: return fp64 ? launch_one<double, 64, 1>(p, stream) : launch_one<float, 64, 1>(p, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+int mfma_leaves_per_block(int D) { return D == 16 ? kNT16 : 1; }
+
+}  // namespace pm

@@ -1,0 +1,661 @@
+// Host runtime of the C ABI declared in include/parament.h: contexts, input
+// validation, the Hermitian basis (drift, controls and the effective
+// commutator controls of eq. magnus_coeffs), Taylor thresholds and
+// planning, engine choice, workspace, and the launches.
+#include <hip/hip_runtime.h>
+
+#include <algorithm>
+#include <cmath>
+#include <complex>
+#include <cstdio>
+#include <cstring>
+#include <new>
+#include <string>
+#include <vector>
+
+#include "pm_internal.h"
+
+namespace pm {
+hipError_t launch_mfma(int D, bool fp64, const PropParams& p, hipStream_t stream);
+hipError_t launch_valu(int D, bool fp64, const PropParams& p, hipStream_t stream);
+int mfma_leaves_per_block(int D);
+}  // namespace pm
+
+using cplx = std::complex<double>;
+
+struct pm_ctx {
+    int device = 0;
+    int precision = PM_FP64;
+    bool ready = false;
+    bool broken = false;
+    int64_t dim = 0;
+    int64_t n_ctrl = 0;
+    int order = 2;
+    int M = 0;
+    pm::EngineInfo eng{};
+    std::vector<double> basis;   // FP64 [M][dim][dim] interleaved
+    std::vector<double> norms;   // [M]
+    uint8_t pair_a[pm::kMaxBasis] = {};
+    uint8_t pair_b[pm::kMaxBasis] = {};
+    double theta[pm::kMaxDeg + 1] = {};
+    int max_degree = PM_MAX_TAYLOR_DEGREE;
+    int force_s = -1;
+    int64_t chunk_override = 0;
+    // device buffers
+    double* d_basis = nullptr;
+    double* d_nodes = nullptr;
+    size_t nodes_bytes = 0;
+    unsigned* d_counters = nullptr;
+    size_t counters_bytes = 0;
+    double* d_samples = nullptr;
+    size_t samples_bytes = 0;
+    double* d_U = nullptr;
+    size_t u_bytes = 0;
+    void* d_slices = nullptr;
+    size_t slices_bytes = 0;
+    std::string err;
+};
+
+namespace {
+
+pm_status fail(pm_ctx* ctx, pm_status s, const std::string& msg) {
+    if (ctx) ctx->err = msg;
+    return s;
+}
+
+pm_status hip_fail(pm_ctx* ctx, hipError_t e, const char* where) {
+    if (ctx) {
+        ctx->broken = true;
+        ctx->err = std::string(where) + ": " + hipGetErrorString(e);
+    }
+    return PM_E_DEVICE;
+}
+
+struct DeviceGuard {
+    int prev = -1;
+    bool ok = true;
+    explicit DeviceGuard(int dev) {
+        if (hipGetDevice(&prev) != hipSuccess) prev = -1;
+        ok = hipSetDevice(dev) == hipSuccess;
+    }
+    ~DeviceGuard() {
+        if (prev >= 0) (void)hipSetDevice(prev);
+    }
+};
+
+double unit_roundoff(int precision) {
+    switch (precision) {
+        case PM_FP64: return std::ldexp(1.0, -53);
+        case PM_FP32:
+        case PM_FP32_3M: return std::ldexp(1.0, -24);
+        case PM_BF16_SPLIT: return std::ldexp(1.0, -16);
+        default: return -1.0;
+    }
+}
+
+// Largest theta with theta^(m+1)/(m+1)! / (1 - theta/(m+2)) <= u.
+double taylor_theta(int m, double u) {
+    auto bound = [m](double th) {
+        double t = 1.0;
+        for (int k = 1; k <= m + 1; ++k) t *= th / k;
+        return t / (1.0 - th / (m + 2));
+    };
+    double lo = 0.0, hi = m + 1.0;   // bound is increasing on [0, m+2)
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (bound(mid) <= u) lo = mid; else hi = mid;
+    }
+    return lo;
+}
+
+int taylor_products_host(int m) {
+    if (m <= 1) return 0;
+    if (m == 2) return 1;
+    return m / 2 + 1;
+}
+
+void plan_host(const double* theta, int md, int force_s, double nu, int* m_out, int* s_out) {
+    auto next = [](int c) { return c < 3 ? c + 1 : c + 2; };
+    if (force_s >= 0) {
+        const double x = std::ldexp(nu, -force_s);
+        int m = md;
+        for (int c = 1; c <= md; c = next(c))
+            if (theta[c] >= x) { m = c; break; }
+        *m_out = m;
+        *s_out = force_s;
+        return;
+    }
+    int bm = md, bs = 0, bc = 1 << 30;
+    for (int s = 0; s < 64; ++s) {
+        if (s >= bc) break;
+        const double x = std::ldexp(nu, -s);
+        for (int c = 1; c <= md; c = next(c)) {
+            if (theta[c] >= x) {
+                const int cost = taylor_products_host(c) + s;
+                if (cost < bc) { bc = cost; bm = c; bs = s; }
+                break;
+            }
+        }
+    }
+    if (bc == (1 << 30)) { bm = md; bs = 0; }
+    *m_out = bm;
+    *s_out = bs;
+}
+
+void fill_theta(double* theta, int precision) {
+    const double u = unit_roundoff(precision);
+    theta[0] = 0.0;
+    for (int m = 1; m <= pm::kMaxDeg; ++m) theta[m] = taylor_theta(m, u);
+}
+
+using Mat = std::vector<cplx>;
+
+Mat load_mat(const double* p, int64_t d) {
+    Mat m(d * d);
+    for (int64_t i = 0; i < d * d; ++i) m[i] = cplx(p[2 * i], p[2 * i + 1]);
+    return m;
+}
+
+Mat matmul(const Mat& a, const Mat& b, int64_t d) {
+    Mat c(d * d, cplx(0, 0));
+    for (int64_t i = 0; i < d; ++i)
+        for (int64_t k = 0; k < d; ++k) {
+            const cplx aik = a[i * d + k];
+            for (int64_t j = 0; j < d; ++j) c[i * d + j] += aik * b[k * d + j];
+        }
+    return c;
+}
+
+// i [A, B] = i (A B - B A): Hermitian when A and B are.
+Mat icomm(const Mat& a, const Mat& b, int64_t d) {
+    Mat ab = matmul(a, b, d), ba = matmul(b, a, d);
+    Mat c(d * d);
+    for (int64_t i = 0; i < d * d; ++i) c[i] = cplx(0, 1) * (ab[i] - ba[i]);
+    return c;
+}
+
+bool hermitian_ok(const Mat& a, int64_t d, bool finite_only = false) {
+    double mx = 0.0, dev = 0.0;
+    for (int64_t i = 0; i < d; ++i)
+        for (int64_t j = 0; j < d; ++j) {
+            const cplx x = a[i * d + j];
+            if (!std::isfinite(x.real()) || !std::isfinite(x.imag())) return false;
+            mx = std::max(mx, std::abs(x));
+            dev = std::max(dev, std::abs(x - std::conj(a[j * d + i])));
+        }
+    return finite_only || dev <= 1e-12 * std::max(1.0, mx);
+}
+
+void symmetrize(Mat& a, int64_t d) {
+    for (int64_t i = 0; i < d; ++i) {
+        a[i * d + i] = cplx(a[i * d + i].real(), 0.0);
+        for (int64_t j = i + 1; j < d; ++j) {
+            const cplx v = 0.5 * (a[i * d + j] + std::conj(a[j * d + i]));
+            a[i * d + j] = v;
+            a[j * d + i] = std::conj(v);
+        }
+    }
+}
+
+double norm1(const Mat& a, int64_t d) {
+    double best = 0.0;
+    for (int64_t j = 0; j < d; ++j) {
+        double s = 0.0;
+        for (int64_t i = 0; i < d; ++i) s += std::abs(a[i * d + j]);
+        best = std::max(best, s);
+    }
+    return best;
+}
+
+// The ordered basis: H0, H_1..H_K [, i[H0,H_k] (k=1..K), i[H_k,H_k'] (k<k')].
+pm_status build_basis(int64_t d, const double* H0, int64_t K, const double* Hk, int order,
+                      std::vector<Mat>* out, std::vector<std::pair<int, int>>* pairs,
+                      std::string* err) {
+    std::vector<Mat> base;
+    base.push_back(load_mat(H0, d));
+    for (int64_t k = 0; k < K; ++k) base.push_back(load_mat(Hk + 2 * k * d * d, d));
+    for (size_t i = 0; i < base.size(); ++i) {
+        if (!hermitian_ok(base[i], d)) {
+            *err = (i == 0 ? std::string("H0") : "H_" + std::to_string(i)) +
+                   " is not Hermitian (or not finite)";
+            return PM_E_NOT_HERMITIAN;
+        }
+        symmetrize(base[i], d);
+    }
+    *out = base;
+    pairs->clear();
+    if (order == 4) {
+        for (int64_t k = 1; k <= K; ++k) {
+            Mat c = icomm(base[0], base[k], d);
+            symmetrize(c, d);
+            out->push_back(c);
+        }
+        for (int64_t a = 1; a <= K; ++a)
+            for (int64_t b = a + 1; b <= K; ++b) {
+                Mat c = icomm(base[a], base[b], d);
+                symmetrize(c, d);
+                out->push_back(c);
+                pairs->push_back({(int)a - 1, (int)b - 1});
+            }
+    }
+    return PM_OK;
+}
+
+template <typename P>
+void dfree(P*& p) {
+    if (p) (void)hipFree((void*)p);
+    p = nullptr;
+}
+
+pm_status ensure(pm_ctx* ctx, void** ptr, size_t* have, size_t need, const char* what,
+                 bool zero = false) {
+    if (need <= *have && *ptr) return PM_OK;
+    if (*ptr) {
+        hipError_t e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+        (void)hipFree(*ptr);
+        *ptr = nullptr;
+        *have = 0;
+    }
+    need = std::max<size_t>(need, 256);
+    hipError_t e = hipMalloc(ptr, need);
+    if (e != hipSuccess) {
+        *ptr = nullptr;
+        (void)hipGetLastError();
+        return fail(ctx, PM_E_OOM, std::string("hipMalloc failed for ") + what);
+    }
+    if (zero) {
+        e = hipMemset(*ptr, 0, need);
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipMemset");
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(ctx, e, "hipDeviceSynchronize");
+    }
+    *have = need;
+    return PM_OK;
+}
+
+int64_t n_slices_of(int order, int64_t n_samples) {
+    return order == 2 ? n_samples : (n_samples - 1) / 2;
+}
+
+pm_status check_prop_args(pm_ctx* ctx, int64_t n_samples, double dt) {
+    if (!ctx) return PM_E_INVALID_ARG;
+    if (ctx->broken) return fail(ctx, PM_E_DEVICE, "context unusable after a device error");
+    if (!ctx->ready) return fail(ctx, PM_E_NOT_READY, "pm_set_hamiltonian has not been called");
+    if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, PM_E_INVALID_ARG, "dt must be finite and > 0");
+    if (ctx->order == 2 && n_samples < 1)
+        return fail(ctx, PM_E_INVALID_ARG, "order 2 needs n_samples >= 1");
+    if (ctx->order == 4 && (n_samples < 3 || (n_samples % 2) == 0))
+        return fail(ctx, PM_E_INVALID_ARG, "order 4 needs an odd n_samples >= 3");
+    if (n_samples > (int64_t(1) << 40)) return fail(ctx, PM_E_INVALID_ARG, "n_samples too large");
+    return PM_OK;
+}
+
+int64_t auto_chunk(const pm::EngineInfo& e, int64_t N) {
+    const int64_t target = 2 * (int64_t)e.resident_leaves;
+    int64_t c = (N + target - 1) / target;
+    if (c < 1) c = 1;
+    const int64_t u = e.leaf_slices_unit;
+    return ((c + u - 1) / u) * u;
+}
+
+pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt, double* d_U,
+                 void* d_slices, hipStream_t stream) {
+    const pm::EngineInfo& e = ctx->eng;
+    const int64_t N = n_slices_of(ctx->order, n_samples);
+    int64_t chunk = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N);
+    chunk = ((chunk + e.leaf_slices_unit - 1) / e.leaf_slices_unit) * e.leaf_slices_unit;
+    const int64_t leaves = (N + chunk - 1) / chunk;
+    const size_t node_bytes = (size_t)e.D * e.D * 16;
+    pm_status st = ensure(ctx, (void**)&ctx->d_nodes, &ctx->nodes_bytes,
+                          node_bytes * (size_t)(2 * leaves + 64), "tree nodes");
+    if (st != PM_OK) return st;
+    st = ensure(ctx, (void**)&ctx->d_counters, &ctx->counters_bytes,
+                sizeof(unsigned) * (size_t)(2 * leaves + 64), "tree tickets", true);
+    if (st != PM_OK) return st;
+
+    pm::PropParams p;
+    std::memset(&p, 0, sizeof(p));
+    p.basis = ctx->d_basis;
+    p.samples = d_samples;
+    p.n_samples = n_samples;
+    p.n_slices = N;
+    p.chunk = chunk;
+    p.n_leaves = leaves;
+    p.slices_out = d_slices;
+    p.nodes = ctx->d_nodes;
+    p.counters = ctx->d_counters;
+    p.U_out = d_U;
+    p.h = dt;
+    std::memcpy(p.theta, ctx->theta, sizeof(p.theta));
+    p.K = (int)ctx->n_ctrl;
+    p.M = ctx->M;
+    p.order = ctx->order;
+    p.du = (int)ctx->dim;
+    p.max_degree = ctx->max_degree;
+    p.force_s = ctx->force_s;
+    std::memcpy(p.pair_a, ctx->pair_a, sizeof(p.pair_a));
+    std::memcpy(p.pair_b, ctx->pair_b, sizeof(p.pair_b));
+    hipError_t he = pm::launch_propagate(e, ctx->precision, p, stream);
+    if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
+    return PM_OK;
+}
+
+}  // namespace
+
+namespace pm {
+
+bool pick_engine(int du, int precision, EngineInfo* out) {
+    if (du < 1 || du > PM_MAX_DIM) return false;
+    if (precision != PM_FP64 && precision != PM_FP32) return false;
+    EngineInfo e{};
+    if (du <= 4) {
+        e.kind = ENGINE_VALU;
+        e.D = du <= 2 ? 2 : 4;
+        e.leaf_slices_unit = 64;
+        e.leaves_per_block = 4;
+        e.resident_leaves = 256 * 8;
+    } else {
+        e.kind = ENGINE_MFMA;
+        e.D = du <= 16 ? 16 : (du <= 32 ? 32 : 64);
+        e.leaf_slices_unit = 1;
+        e.leaves_per_block = mfma_leaves_per_block(e.D);
+        e.resident_leaves = e.D == 16 ? 256 * 8 : (e.D == 32 ? 256 * 4 : 256);
+        e.f64_rows = precision == PM_FP64 ? 1 : 0;
+    }
+    *out = e;
+    return true;
+}
+
+int64_t basis_layout_doubles(const EngineInfo& e, int M) {
+    return (int64_t)M * e.D * e.D * 2;
+}
+
+void basis_to_layout(const EngineInfo& e, int M, int du, const double* basis, double* dst) {
+    const int D = e.D;
+    std::memset(dst, 0, sizeof(double) * basis_layout_doubles(e, M));
+    for (int m = 0; m < M; ++m) {
+        const double* b = basis + (int64_t)m * du * du * 2;
+        for (int r = 0; r < du; ++r)
+            for (int c = 0; c < du; ++c) {
+                const double re = b[(r * du + c) * 2], im = b[(r * du + c) * 2 + 1];
+                if (e.kind == ENGINE_VALU) {
+                    dst[((int64_t)m * D * D + r * D + c) * 2 + 0] = re;
+                    dst[((int64_t)m * D * D + r * D + c) * 2 + 1] = im;
+                } else {
+                    const int TI = r / 16, TJ = c / 16, rr = r % 16, cc = c % 16;
+                    const int g = e.f64_rows ? rr % 4 : rr / 4;
+                    const int ri = e.f64_rows ? rr / 4 : rr % 4;
+                    const int lane = 16 * g + cc;
+                    dst[mfma_basis_index(D, m, TI, TJ, 0, ri, lane)] = re;
+                    dst[mfma_basis_index(D, m, TI, TJ, 1, ri, lane)] = im;
+                }
+            }
+    }
+}
+
+hipError_t launch_propagate(const EngineInfo& e, int precision, const PropParams& p,
+                            hipStream_t stream) {
+    const bool fp64 = precision == PM_FP64;
+    if (e.kind == ENGINE_VALU) return launch_valu(e.D, fp64, p, stream);
+    return launch_mfma(e.D, fp64, p, stream);
+}
+
+}  // namespace pm
+
+// ------------------------------------------------------------------ C ABI
+
+extern "C" {
+
+const char* pm_status_string(pm_status s) {
+    switch (s) {
+        case PM_OK: return "PM_OK";
+        case PM_E_INVALID_ARG: return "PM_E_INVALID_ARG";
+        case PM_E_NOT_READY: return "PM_E_NOT_READY";
+        case PM_E_NOT_HERMITIAN: return "PM_E_NOT_HERMITIAN";
+        case PM_E_OOM: return "PM_E_OOM";
+        case PM_E_DEVICE: return "PM_E_DEVICE";
+        case PM_E_UNSUPPORTED: return "PM_E_UNSUPPORTED";
+    }
+    return "PM_E_UNKNOWN";
+}
+
+const char* pm_last_error(const pm_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+
+int64_t pm_basis_count(int64_t n_ctrl, int order) {
+    if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl) return -1;
+    if (order == 2) return 1 + n_ctrl;
+    if (order == 4) return 1 + 2 * n_ctrl + n_ctrl * (n_ctrl - 1) / 2;
+    return -1;
+}
+
+pm_status pm_taylor_theta(int m, int precision, double* theta_out) {
+    if (m < 1 || m > PM_MAX_TAYLOR_DEGREE || !theta_out) return PM_E_INVALID_ARG;
+    const double u = unit_roundoff(precision);
+    if (u < 0) return PM_E_INVALID_ARG;
+    *theta_out = taylor_theta(m, u);
+    return PM_OK;
+}
+
+pm_status pm_plan_expm(double nu, int precision, int max_degree, int* m_out, int* s_out) {
+    if (!m_out || !s_out || !(nu >= 0.0) || max_degree < 1 || max_degree > PM_MAX_TAYLOR_DEGREE)
+        return PM_E_INVALID_ARG;
+    if (unit_roundoff(precision) < 0) return PM_E_INVALID_ARG;
+    double th[pm::kMaxDeg + 1];
+    fill_theta(th, precision);
+    plan_host(th, max_degree, -1, nu, m_out, s_out);
+    return PM_OK;
+}
+
+pm_status pm_build_basis_host(int64_t dim, const double* H0, int64_t n_ctrl, const double* Hk,
+                              int order, double* basis_out, double* norms_out) {
+    if (dim < 1 || dim > PM_MAX_DIM || !H0 || n_ctrl < 0 || n_ctrl > pm::kMaxCtrl ||
+        (n_ctrl > 0 && !Hk) || (order != 2 && order != 4))
+        return PM_E_INVALID_ARG;
+    std::vector<Mat> basis;
+    std::vector<std::pair<int, int>> pairs;
+    std::string err;
+    pm_status s = build_basis(dim, H0, n_ctrl, Hk, order, &basis, &pairs, &err);
+    if (s != PM_OK) return s;
+    for (size_t m = 0; m < basis.size(); ++m) {
+        if (basis_out)
+            for (int64_t i = 0; i < dim * dim; ++i) {
+                basis_out[(m * dim * dim + i) * 2 + 0] = basis[m][i].real();
+                basis_out[(m * dim * dim + i) * 2 + 1] = basis[m][i].imag();
+            }
+        if (norms_out) norms_out[m] = norm1(basis[m], dim);
+    }
+    return PM_OK;
+}
+
+pm_status pm_slice_weights_host(int64_t n_ctrl, const double* samples, int64_t n_samples,
+                                double dt, int order, int64_t slice, double* weights_out) {
+    if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl || (n_ctrl > 0 && !samples) || !weights_out ||
+        (order != 2 && order != 4))
+        return PM_E_INVALID_ARG;
+    if (order == 4 && (n_samples < 3 || (n_samples % 2) == 0)) return PM_E_INVALID_ARG;
+    const int64_t N = n_slices_of(order, n_samples);
+    if (slice < 0 || slice >= N) return PM_E_INVALID_ARG;
+    const int64_t K = n_ctrl, S = n_samples;
+    const double h = dt;
+    int64_t m = 0;
+    weights_out[m++] = h;
+    if (order == 2) {
+        for (int64_t k = 0; k < K; ++k) weights_out[m++] = h * samples[k * S + slice];
+        return PM_OK;
+    }
+    auto s = [&](int64_t k, int i) { return samples[k * S + 2 * slice + i]; };
+    for (int64_t k = 0; k < K; ++k) weights_out[m++] = (h / 6.0) * (s(k, 0) + 4.0 * s(k, 1) + s(k, 2));
+    const double h2 = h * h / 12.0;
+    for (int64_t k = 0; k < K; ++k) weights_out[m++] = h2 * (s(k, 2) - s(k, 0));
+    for (int64_t a = 0; a < K; ++a)
+        for (int64_t b = a + 1; b < K; ++b) weights_out[m++] = h2 * (s(a, 0) * s(b, 2) - s(a, 2) * s(b, 0));
+    return PM_OK;
+}
+
+pm_status pm_create(pm_ctx** out, int device, int precision) {
+    if (!out) return PM_E_INVALID_ARG;
+    *out = nullptr;
+    if (unit_roundoff(precision) < 0) return PM_E_INVALID_ARG;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return PM_E_DEVICE;
+    }
+    if (device < 0 || device >= n) return PM_E_INVALID_ARG;
+    pm_ctx* ctx = new (std::nothrow) pm_ctx();
+    if (!ctx) return PM_E_OOM;
+    ctx->device = device;
+    ctx->precision = precision;
+    fill_theta(ctx->theta, precision);
+    *out = ctx;
+    return PM_OK;
+}
+
+pm_status pm_destroy(pm_ctx* ctx) {
+    if (!ctx) return PM_OK;
+    {
+        DeviceGuard g(ctx->device);
+        (void)hipDeviceSynchronize();
+        dfree(ctx->d_basis);
+        dfree(ctx->d_nodes);
+        dfree(ctx->d_counters);
+        dfree(ctx->d_samples);
+        dfree(ctx->d_U);
+        if (ctx->d_slices) (void)hipFree(ctx->d_slices);
+        ctx->d_slices = nullptr;
+    }
+    delete ctx;
+    return PM_OK;
+}
+
+pm_status pm_set_expm_policy(pm_ctx* ctx, int max_taylor_degree, int force_s) {
+    if (!ctx) return PM_E_INVALID_ARG;
+    if (max_taylor_degree < 1 || max_taylor_degree > PM_MAX_TAYLOR_DEGREE || force_s < -1 || force_s > 62)
+        return fail(ctx, PM_E_INVALID_ARG, "max_taylor_degree in [1, 21], force_s in [-1, 62]");
+    ctx->max_degree = max_taylor_degree;
+    ctx->force_s = force_s;
+    return PM_OK;
+}
+
+pm_status pm_set_chunk(pm_ctx* ctx, int64_t chunk) {
+    if (!ctx || chunk < 0) return ctx ? fail(ctx, PM_E_INVALID_ARG, "chunk must be >= 0") : PM_E_INVALID_ARG;
+    ctx->chunk_override = chunk;
+    return PM_OK;
+}
+
+pm_status pm_set_hamiltonian(pm_ctx* ctx, int64_t dim, const double* H0, int64_t n_ctrl,
+                             const double* Hk, int order) {
+    if (!ctx) return PM_E_INVALID_ARG;
+    if (ctx->broken) return fail(ctx, PM_E_DEVICE, "context unusable after a device error");
+    if (dim < 1 || dim > PM_MAX_DIM) return fail(ctx, PM_E_INVALID_ARG, "dim must be in [1, 64]");
+    if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl) return fail(ctx, PM_E_INVALID_ARG, "n_ctrl must be in [0, 8]");
+    if (order != 2 && order != 4) return fail(ctx, PM_E_INVALID_ARG, "order must be 2 or 4");
+    if (!H0 || (n_ctrl > 0 && !Hk)) return fail(ctx, PM_E_INVALID_ARG, "null Hamiltonian pointer");
+    pm::EngineInfo e;
+    if (!pm::pick_engine((int)dim, ctx->precision, &e))
+        return fail(ctx, PM_E_UNSUPPORTED, "no engine for this dimension / precision");
+    std::vector<Mat> basis;
+    std::vector<std::pair<int, int>> pairs;
+    std::string err;
+    pm_status s = build_basis(dim, H0, n_ctrl, Hk, order, &basis, &pairs, &err);
+    if (s != PM_OK) return fail(ctx, s, err);
+    const int M = (int)basis.size();
+    std::vector<double> flat((size_t)M * dim * dim * 2), norms(M);
+    for (int m = 0; m < M; ++m) {
+        for (int64_t i = 0; i < dim * dim; ++i) {
+            flat[((size_t)m * dim * dim + i) * 2 + 0] = basis[m][i].real();
+            flat[((size_t)m * dim * dim + i) * 2 + 1] = basis[m][i].imag();
+        }
+        norms[m] = norm1(basis[m], dim);
+    }
+    std::vector<double> lay((size_t)pm::basis_layout_doubles(e, M));
+    pm::basis_to_layout(e, M, (int)dim, flat.data(), lay.data());
+
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    hipError_t he = hipDeviceSynchronize();
+    if (he != hipSuccess) return hip_fail(ctx, he, "hipDeviceSynchronize");
+    dfree(ctx->d_basis);
+    he = hipMalloc((void**)&ctx->d_basis, lay.size() * sizeof(double));
+    if (he != hipSuccess) {
+        ctx->d_basis = nullptr;
+        (void)hipGetLastError();
+        ctx->ready = false;
+        return fail(ctx, PM_E_OOM, "hipMalloc failed for the basis");
+    }
+    he = hipMemcpy(ctx->d_basis, lay.data(), lay.size() * sizeof(double), hipMemcpyHostToDevice);
+    if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy basis");
+    ctx->dim = dim;
+    ctx->n_ctrl = n_ctrl;
+    ctx->order = order;
+    ctx->M = M;
+    ctx->eng = e;
+    ctx->basis = flat;
+    ctx->norms = norms;
+    std::memset(ctx->pair_a, 0, sizeof(ctx->pair_a));
+    std::memset(ctx->pair_b, 0, sizeof(ctx->pair_b));
+    for (size_t q = 0; q < pairs.size(); ++q) {
+        const int m = 1 + 2 * (int)n_ctrl + (int)q;
+        ctx->pair_a[m] = (uint8_t)pairs[q].first;
+        ctx->pair_b[m] = (uint8_t)pairs[q].second;
+    }
+    ctx->ready = true;
+    ctx->err.clear();
+    return PM_OK;
+}
+
+pm_status pm_equiprop_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samples, double dt,
+                          double* U_out_dev, void* slices_out_dev, void* stream) {
+    pm_status s = check_prop_args(ctx, n_samples, dt);
+    if (s != PM_OK) return s;
+    if (!U_out_dev) return fail(ctx, PM_E_INVALID_ARG, "U_out is null");
+    if (ctx->n_ctrl > 0 && !samples_dev) return fail(ctx, PM_E_INVALID_ARG, "samples is null");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    return launch(ctx, samples_dev, n_samples, dt, U_out_dev, slices_out_dev, (hipStream_t)stream);
+}
+
+pm_status pm_equiprop(pm_ctx* ctx, const double* samples, int64_t n_samples, double dt,
+                      double* U_out, void* slices_out) {
+    pm_status s = check_prop_args(ctx, n_samples, dt);
+    if (s != PM_OK) return s;
+    if (!U_out) return fail(ctx, PM_E_INVALID_ARG, "U_out is null");
+    if (ctx->n_ctrl > 0 && !samples) return fail(ctx, PM_E_INVALID_ARG, "samples is null");
+    const int64_t K = ctx->n_ctrl;
+    for (int64_t i = 0; i < K * n_samples; ++i)
+        if (!std::isfinite(samples[i])) return fail(ctx, PM_E_INVALID_ARG, "non-finite control sample");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    const int64_t N = n_slices_of(ctx->order, n_samples);
+    const size_t sbytes = sizeof(double) * (size_t)std::max<int64_t>(K * n_samples, 1);
+    s = ensure(ctx, (void**)&ctx->d_samples, &ctx->samples_bytes, sbytes, "samples");
+    if (s != PM_OK) return s;
+    s = ensure(ctx, (void**)&ctx->d_U, &ctx->u_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "U");
+    if (s != PM_OK) return s;
+    const size_t elem = ctx->precision == PM_FP64 ? 16 : 8;
+    const size_t slbytes = elem * (size_t)N * ctx->dim * ctx->dim;
+    if (slices_out) {
+        s = ensure(ctx, &ctx->d_slices, &ctx->slices_bytes, slbytes, "slices");
+        if (s != PM_OK) return s;
+    }
+    hipError_t he = hipSuccess;
+    if (K > 0) {
+        he = hipMemcpy(ctx->d_samples, samples, sizeof(double) * K * n_samples, hipMemcpyHostToDevice);
+        if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy samples");
+    }
+    s = launch(ctx, ctx->d_samples, n_samples, dt, ctx->d_U, slices_out ? ctx->d_slices : nullptr,
+               nullptr);
+    if (s != PM_OK) return s;
+    he = hipDeviceSynchronize();
+    if (he != hipSuccess) return hip_fail(ctx, he, "kernel execution");
+    he = hipMemcpy(U_out, ctx->d_U, 16 * ctx->dim * ctx->dim, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy U");
+    if (slices_out) {
+        he = hipMemcpy(slices_out, ctx->d_slices, slbytes, hipMemcpyDeviceToHost);
+        if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy slices");
+    }
+    return PM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,74 @@
+// Internal interface between the host runtime (parament.cpp) and the HIP
+// engines.  Not part of the public ABI.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/parament.h"
+
+namespace pm {
+
+constexpr int kMaxCtrl = 8;
+constexpr int kMaxBasis = 1 + 2 * kMaxCtrl + kMaxCtrl * (kMaxCtrl - 1) / 2;  // 45
+constexpr int kMaxDeg = PM_MAX_TAYLOR_DEGREE;
+
+// Everything one propagation launch needs, passed by value as the kernel
+// argument.  Pointers are device pointers.
+struct PropParams {
+    const double* basis;      // Hermitian basis in the engine's layout, FP64
+    const double* samples;    // [K][n_samples]
+    int64_t n_samples;
+    int64_t n_slices;         // N
+    int64_t chunk;            // consecutive slices per leaf
+    int64_t n_leaves;         // ceil(N / chunk)
+    void* slices_out;         // nullptr or [N][du][du] complex (c128 / c64)
+    double* nodes;            // tree nodes, [2 * n_leaves][D][D] complex128
+    unsigned* counters;       // [2 * n_leaves] pair tickets, zero between launches
+    double* U_out;            // [du][du] complex128
+    double h;
+    double theta[kMaxDeg + 1];   // Taylor thresholds for the working precision
+    int K, M, order, du;
+    int max_degree, force_s;
+    uint8_t pair_a[kMaxBasis];   // order 4: control indices of i[H_a, H_b]
+    uint8_t pair_b[kMaxBasis];
+};
+
+// Engines.  D is the (padded) engine dimension.
+//   MFMA engine: D in {16, 32, 64}; one team of (D/16)^2 waves per slice
+//   chain, every wave owning one 16x16 output tile.
+//   VALU engine: D in {2, 4}; one slice per lane.
+enum EngineKind { ENGINE_VALU = 0, ENGINE_MFMA = 1 };
+
+struct EngineInfo {
+    int kind;
+    int D;                 // engine dimension
+    int leaf_slices_unit;  // a leaf's chunk is a multiple of this
+    int leaves_per_block;  // teams (MFMA) or waves (VALU) per block
+    int resident_leaves;   // leaves the whole GPU runs at once (rough)
+    int f64_rows;          // MFMA: accumulator rows interleaved as in FP64 (g + 4r)
+};
+
+// Engine choice for a user dimension; false if unsupported.
+bool pick_engine(int du, int precision, EngineInfo* out);
+
+// Basis layout of the engine, filled from the FP64 basis [M][du][du]
+// (interleaved complex, row-major) into `dst` (host memory, size from
+// basis_layout_doubles).
+int64_t basis_layout_doubles(const EngineInfo& e, int M);
+void basis_to_layout(const EngineInfo& e, int M, int du, const double* basis, double* dst);
+
+hipError_t launch_propagate(const EngineInfo& e, int precision, const PropParams& p,
+                            hipStream_t stream);
+
+// MFMA basis layout: [m][tile][plane][r][lane] with tile = TI*(D/16)+TJ,
+// lane = 16 g + j holding element (16 TI + row(g, r), 16 TJ + j), where
+// row(g, r) = g + 4 r for FP64 kernels and 4 g + r for FP32 kernels (the
+// accumulator layouts of the two 16x16x4 MFMA instructions).
+__host__ __device__ inline int64_t mfma_basis_index(int D, int m, int TI, int TJ, int plane,
+                                                    int r, int lane) {
+    const int TD = D / 16;
+    return ((((int64_t)m * TD * TD + TI * TD + TJ) * 2 + plane) * 4 + r) * 64 + lane;
+}
+
+}  // namespace pm

@@ -1,0 +1,204 @@
+"""Parity of the HIP path with the FP64 oracle, through the C ABI.
+
+FP64 bar: relative Frobenius error of U(T) <= 1e-10, per-slice propagators
+within 1e-13 max-abs.  FP32 (complex64) bar, derived from the arithmetic:
+each product of d-term sums carries ~d u32 relative error and N chained
+products add up at most like sqrt(N) in practice, so
+    tol32(N, d) = 4 sqrt(N) d u32 + 1e-6,   u32 = 2^-24.
+"""
+import math
+import sys
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle.propagator as orc
+import synth
+
+pytestmark = pytest.mark.gpu
+
+TOL64 = 1e-10
+U32 = 2.0 ** -24
+
+
+def tol32(n, d):
+    return 4.0 * math.sqrt(n) * d * U32 + 1e-6
+
+
+def say(*a):
+    print(*a, file=sys.stderr, flush=True)
+
+
+@pytest.fixture(scope="module")
+def pm():
+    import torch
+    if not torch.cuda.is_available():
+        pytest.skip("no GPU")
+    import paper_2108_07126_amd as m
+    return m
+
+
+def run(pm, w, precision=0, slices=False, chunk=0, force_s=-1, max_deg=21):
+    say(f"[case] {w.name} d={w.dim} K={w.n_ctrl} N={w.n_slices} order={w.order} prec={precision} "
+        f"chunk={chunk} force_s={force_s}")
+    with pm.Context(0, precision) as ctx:
+        ctx.set_hamiltonian(w.H0, w.Hk, w.order)
+        if chunk:
+            ctx.set_chunk(chunk)
+        if force_s >= 0 or max_deg != 21:
+            ctx.set_expm_policy(max_deg, force_s)
+        return ctx.equiprop(w.samples, w.h, return_slices=slices)
+
+
+def test_driven_qubit_full_size_fp64(pm):
+    w = synth.driven_qubit()
+    U, sl = run(pm, w, slices=True)
+    Uo, slo = orc.propagate(w.H0, w.Hk, w.samples, w.h, w.order, return_slices=True)
+    assert orc.relative_frobenius(U, Uo) <= TOL64
+    assert np.max(np.abs(sl - slo)) <= 1e-13
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("d", [1, 2, 3, 4, 5, 8, 12, 16, 17, 32, 40, 64])
+def test_dims_orders_ragged_fp64(pm, d, order):
+    K = 2 if d > 1 else 1
+    for n in (1, 3, 77):
+        w = synth.random_system(d, K, n_slices=n, h=0.07, order=order, tag=n)
+        U, sl = run(pm, w, slices=True)
+        Uo, slo = orc.propagate(w.H0, w.Hk, w.samples, w.h, order, return_slices=True)
+        assert orc.relative_frobenius(U, Uo) <= TOL64, (d, order, n)
+        assert np.max(np.abs(sl - slo)) <= 1e-13, (d, order, n)
+
+
+@pytest.mark.parametrize("d", [2, 4, 16, 32, 64])
+def test_dims_many_slices_fp64_and_fp32(pm, d):
+    n = 1000 if d < 64 else 300
+    w = synth.random_system(d, 3, n_slices=n, h=0.02, order=4, tag=5)
+    Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 4)
+    assert orc.relative_frobenius(run(pm, w), Uo) <= TOL64
+    e32 = orc.relative_frobenius(run(pm, w, precision=pm.PM_FP32), Uo)
+    say(f"  fp32 rel err {e32:.3e} (bound {tol32(n, d):.3e})")
+    assert e32 <= tol32(n, d)
+
+
+def test_random_qudit_reduced_fp64_fp32(pm):
+    w = synth.random_qudit(n_slices=4096)
+    U, sl = run(pm, w, slices=True)
+    Uo, slo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 4, return_slices=True)
+    assert orc.relative_frobenius(U, Uo) <= TOL64
+    assert np.max(np.abs(sl - slo)) <= 1e-13
+    U32v, sl32 = run(pm, w, precision=pm.PM_FP32, slices=True)
+    assert sl32.dtype == np.complex64
+    assert orc.relative_frobenius(U32v, Uo) <= tol32(4096, 16)
+    assert np.max(np.abs(sl32 - slo)) <= 16 * 16 * U32
+
+
+def test_random_qudit_full_size_fp64(pm):
+    """The full workload (d=16, N=2^17, order 4): U(T) against the oracle's
+    full sequential product; per-slice output sampled at 64 slices."""
+    w = synth.random_qudit()
+    U, sl = run(pm, w, slices=True)
+    Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 4)
+    err = orc.relative_frobenius(U, Uo)
+    say(f"  full-size rel err {err:.3e}")
+    assert err <= TOL64
+    rng = np.random.default_rng(0)
+    js = np.sort(rng.choice(w.n_slices, 64, replace=False))
+    for j in js:
+        G = orc.slice_exponents(w.H0, w.Hk, w.samples, w.h, 4, j, j + 1)
+        assert np.max(np.abs(sl[j] - orc.expm_minus_i(G)[0])) <= 1e-13
+
+
+def test_precision_sweep_reduced(pm):
+    w = synth.precision_sweep(n_slices=512)
+    Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 2)
+    assert orc.relative_frobenius(run(pm, w), Uo) <= TOL64
+    e32 = orc.relative_frobenius(run(pm, w, precision=pm.PM_FP32), Uo)
+    say(f"  d=64 fp32 rel err {e32:.3e}")
+    assert e32 <= tol32(512, 64)
+
+
+def test_qubit_register_fp64(pm):
+    w = synth.qubit_register()
+    Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 2)
+    assert orc.relative_frobenius(run(pm, w), Uo) <= TOL64
+
+
+@pytest.mark.parametrize("d", [2, 16])
+def test_static_hamiltonian_exact(pm, d):
+    """Constant controls: U(T) = exp(-i H T) by scipy's Pade expm."""
+    w = synth.random_system(d, 2, n_slices=500, h=0.01, order=2, tag=9)
+    c = np.repeat(np.array([[0.4], [-0.9]]), 500, axis=1)
+    H = w.H0 + 0.4 * w.Hk[0] - 0.9 * w.Hk[1]
+    with pm.Context() as ctx:
+        ctx.set_hamiltonian(w.H0, w.Hk, 2)
+        U = ctx.equiprop(c, 0.01)
+    assert orc.relative_frobenius(U, scipy.linalg.expm(-1j * H * 5.0)) <= TOL64
+
+
+@pytest.mark.parametrize("d", [2, 4, 16, 32])
+def test_forced_and_large_norm_squarings(pm, d):
+    w = synth.random_system(d, 2, n_slices=50, h=0.9, order=2, tag=3, h0_norm=20.0)
+    Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 2)
+    assert orc.relative_frobenius(run(pm, w), Uo) <= TOL64          # auto: s > 0
+    assert orc.relative_frobenius(run(pm, w, force_s=9), Uo) <= TOL64
+    e32 = orc.relative_frobenius(run(pm, w, precision=pm.PM_FP32), Uo)
+    assert e32 <= tol32(50, d) * 64  # 2^s error growth of the FP32 Taylor step (s ~ 6)
+
+
+@pytest.mark.parametrize("d", [2, 16, 32])
+def test_chunking_and_tree_shape_invariance(pm, d):
+    """Chain lengths 1 (pure tree), ragged and large give the same U(T); the
+    same configuration twice is bitwise identical."""
+    w = synth.random_system(d, 2, n_slices=1333, h=0.03, order=2, tag=4)
+    ref = run(pm, w, chunk=64 if d <= 4 else 7)
+    for ch in ((64, 128, 1344) if d <= 4 else (1, 64, 1333)):
+        U = run(pm, w, chunk=ch)
+        assert orc.relative_frobenius(U, ref) <= 1e-13
+    again = run(pm, w, chunk=64 if d <= 4 else 7)
+    assert np.array_equal(again, ref)
+
+
+def test_state_machine_and_errors(pm):
+    with pm.Context() as ctx:
+        with pytest.raises(pm.ParamentError) as e:
+            ctx.dim, ctx.order = 2, 2
+            ctx.equiprop(np.zeros((1, 4)), 0.1)
+        assert e.value.name == "PM_E_NOT_READY"
+        with pytest.raises(pm.ParamentError) as e:
+            ctx.set_hamiltonian(np.array([[0, 1], [0, 0]], complex), np.zeros((0, 2, 2)), 2)
+        assert e.value.name == "PM_E_NOT_HERMITIAN"
+        ctx.set_hamiltonian(synth.PAULI_Z, synth.PAULI_X[None], 4)
+        for bad in (np.zeros((1, 4)), np.zeros((1, 1))):
+            with pytest.raises(pm.ParamentError) as e:
+                ctx.equiprop(bad, 0.1)
+            assert e.value.name == "PM_E_INVALID_ARG"
+        with pytest.raises(pm.ParamentError):
+            ctx.equiprop(np.zeros((1, 5)), -0.1)
+        with pytest.raises(pm.ParamentError):
+            ctx.equiprop(np.full((1, 5), np.nan), 0.1)
+        # still usable
+        U = ctx.equiprop(np.zeros((1, 5)), 0.1)
+        assert orc.relative_frobenius(U, scipy.linalg.expm(-1j * synth.PAULI_Z * 0.2)) <= TOL64
+        with pytest.raises(pm.ParamentError) as e:
+            ctx.set_hamiltonian(np.eye(65, dtype=complex), np.zeros((0, 65, 65)), 2)
+        assert e.value.name == "PM_E_INVALID_ARG"
+
+
+def test_device_entry_point_matches_host(pm):
+    import torch
+    w = synth.random_system(16, 3, n_slices=999, h=0.02, order=4, tag=8)
+    with pm.Context() as ctx:
+        ctx.set_hamiltonian(w.H0, w.Hk, 4)
+        Uh, slh = ctx.equiprop(w.samples, w.h, return_slices=True)
+        s = torch.from_numpy(w.samples).cuda()
+        U = torch.zeros((16, 16), dtype=torch.complex128, device="cuda")
+        sl = torch.zeros((999, 16, 16), dtype=torch.complex128, device="cuda")
+        st = torch.cuda.Stream()
+        st.wait_stream(torch.cuda.current_stream())
+        with torch.cuda.stream(st):
+            ctx.equiprop_dev(s, w.h, U, sl)
+        st.synchronize()
+        assert np.array_equal(U.cpu().numpy(), Uh)
+        assert np.array_equal(sl.cpu().numpy(), slh)

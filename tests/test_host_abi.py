@@ -1,0 +1,153 @@
+"""CPU tests of the library's host side: ABI exports, the Hermitian basis and
+slice weights of the expand step, Taylor thresholds and the (m, s) planner.
+No GPU is touched."""
+import math
+import os
+import re
+
+import numpy as np
+import pytest
+import scipy.linalg
+
+import oracle.propagator as orc
+import synth
+
+pm = pytest.importorskip("paper_2108_07126_amd")
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+
+
+def header_symbols():
+    syms = set()
+    for fn in os.listdir(os.path.join(ROOT, "include")):
+        if fn.endswith(".h"):
+            txt = open(os.path.join(ROOT, "include", fn)).read()
+            txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+            syms |= set(re.findall(r"\b(pm_[a-z0-9_]+)\s*\(", txt))
+    return syms
+
+
+def test_library_exports_every_declared_symbol():
+    syms = header_symbols()
+    assert len(syms) >= 14
+    for s in sorted(syms):
+        assert hasattr(pm._lib, s), s
+    # the binding declares a signature for each one
+    assert syms == set(pm.SIGNATURES), syms ^ set(pm.SIGNATURES)
+
+
+def test_status_strings():
+    for i, name in enumerate(pm.STATUS):
+        assert pm._lib.pm_status_string(i).decode() == name
+
+
+def test_basis_count_matches_effective_control_count():
+    for K in range(0, 9):
+        assert pm.basis_count(K, 2) == 1 + K
+        # 3K/2 + K^2/2 effective controls besides H0 (eq. magnus_coeffs)
+        assert pm.basis_count(K, 4) - 1 == (3 * K + K * K) // 2
+    assert pm.basis_count(9, 2) == -1
+    assert pm.basis_count(2, 3) == -1
+
+
+@pytest.mark.parametrize("order", [2, 4])
+@pytest.mark.parametrize("d,K", [(2, 1), (5, 3), (16, 3), (8, 4)])
+def test_expand_matches_oracle_slice_exponents(order, d, K):
+    """sum_m w_{j,m} B_m (host basis and weights) equals the oracle's directly
+    assembled exponent (commutator formed from A1, A3) to rounding."""
+    w = synth.random_system(d, K, n_slices=7, h=0.05, order=order, tag=d * 10 + K)
+    B, norms = pm.build_basis_host(w.H0, w.Hk, order)
+    assert B.shape[0] == pm.basis_count(K, order)
+    for m in range(B.shape[0]):
+        assert np.max(np.abs(B[m] - B[m].conj().T)) == 0.0
+        assert abs(norms[m] - np.max(np.sum(np.abs(B[m]), axis=0))) < 1e-13 * max(1, norms[m])
+    Gref = orc.slice_exponents(w.H0, w.Hk, w.samples, w.h, order)
+    for j in range(w.n_slices):
+        wt = pm.slice_weights_host(w.samples, w.h, order, j)
+        G = np.tensordot(wt, B, axes=1)
+        assert np.max(np.abs(G - Gref[j])) < 1e-14 * max(1.0, np.max(np.abs(Gref[j])))
+
+
+def test_non_hermitian_rejected():
+    H0 = np.array([[1.0, 0.5], [0.4, -1.0]], complex)
+    with pytest.raises(pm.ParamentError) as e:
+        pm.build_basis_host(H0, np.zeros((0, 2, 2)), 2)
+    assert e.value.name == "PM_E_NOT_HERMITIAN"
+    H0 = np.array([[1.0, np.nan], [np.nan, -1.0]], complex)
+    with pytest.raises(pm.ParamentError):
+        pm.build_basis_host(H0, np.zeros((0, 2, 2)), 2)
+
+
+def test_bad_arguments_rejected():
+    with pytest.raises(pm.ParamentError):
+        pm.slice_weights_host(np.zeros((1, 4)), 0.1, 4, 0)  # order 4 needs an odd count
+    with pytest.raises(pm.ParamentError):
+        pm.taylor_theta(0)
+    with pytest.raises(pm.ParamentError):
+        pm.plan_expm(-1.0)
+
+
+def _taylor(X, m):
+    T = np.eye(X.shape[0], dtype=complex)
+    P = np.eye(X.shape[0], dtype=complex)
+    for k in range(1, m + 1):
+        P = P @ X / k
+        T = T + P
+    return T
+
+
+@pytest.mark.parametrize("prec,u", [(pm.PM_FP64, 2.0 ** -53), (pm.PM_FP32, 2.0 ** -24),
+                                    (pm.PM_BF16_SPLIT, 2.0 ** -16)])
+def test_taylor_theta_bounds_truncation(prec, u):
+    """theta_m makes the remainder bound equal u, and the true truncation error
+    of exp(X) - T_m(X) at ||X||_1 = theta_m (X skew-Hermitian) stays below it."""
+    rng = np.random.default_rng(4)
+    prev = 0.0
+    for m in range(1, 22):
+        th = pm.taylor_theta(m, prec)
+        assert th > prev
+        prev = th
+        bound = th ** (m + 1) / math.factorial(m + 1) / (1 - th / (m + 2))
+        assert abs(bound - u) < 1e-6 * u
+        if 3 <= m <= 15:
+            A = rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6))
+            G = 0.5 * (A + A.conj().T)
+            G *= th / np.max(np.sum(np.abs(G), axis=0))
+            X = -1j * G
+            err = np.linalg.norm(scipy.linalg.expm(X) - _taylor(X, m), 1)
+            assert err <= 1.5 * u + 64 * 2.0 ** -53
+
+
+def _cost(m):
+    return 0 if m <= 1 else (1 if m == 2 else m // 2 + 1)
+
+
+@pytest.mark.parametrize("prec", [pm.PM_FP64, pm.PM_FP32, pm.PM_BF16_SPLIT])
+def test_planner_is_feasible_and_optimal(prec):
+    th = {m: pm.taylor_theta(m, prec) for m in range(1, 22)}
+    for nu in [0.0, 1e-9, 3e-4, 0.0043, 0.0346, 0.195, 0.43, 1.0, 3.7, 40.0, 1e4]:
+        m, s = pm.plan_expm(nu, prec)
+        assert nu / 2 ** s <= th[m]
+        # brute force over all feasible (m', s')
+        best = min(_cost(mm) + ss for ss in range(0, 40) for mm in th if nu / 2 ** ss <= th[mm])
+        assert _cost(m) + s == best
+    # tie goes to the smaller s
+    m, s = pm.plan_expm(0.0043, pm.PM_FP64)
+    assert (m, s) == (5, 0)
+
+
+def test_create_without_device_reports_device_error():
+    import ctypes
+    try:
+        import torch
+        has_gpu = torch.cuda.is_available()
+    except Exception:
+        has_gpu = False
+    h = ctypes.c_void_p()
+    st = pm._lib.pm_create(ctypes.byref(h), 0, pm.PM_FP64)
+    if has_gpu:
+        assert st == 0
+        pm._lib.pm_destroy(h)
+    else:
+        assert pm.STATUS[st] == "PM_E_DEVICE"
+    assert pm.STATUS[pm._lib.pm_create(ctypes.byref(h), 0, 7)] == "PM_E_INVALID_ARG"
