@@ -159,17 +159,23 @@ pm_status pm_slice_weights_host(int64_t n_ctrl, const double *samples,
                                 int64_t n_samples, double dt, int order,
                                 int64_t slice, double *weights_out);
 
-/* Truncation threshold theta_m of the degree-m Taylor polynomial for the
- * precision's unit roundoff u (2^-53 FP64, 2^-24 FP32 modes, 2^-16 BF16
- * split): the largest theta with theta^(m+1)/(m+1)! / (1 - theta/(m+2)) <= u,
- * which bounds the remainder of exp(X) - T_m(X) for ||X|| <= theta. */
-pm_status pm_taylor_theta(int m, int precision, double *theta_out);
+/* Truncation threshold theta_m of the degree-m Taylor polynomial used for a
+ * propagation of n_slices slices: the largest theta with
+ *     theta^(m+1)/(m+1)! / (1 - theta/(m+2)) <= u_t,
+ * which bounds the remainder of exp(X) - T_m(X) for ||X|| <= theta, with the
+ * truncation target u_t = max(2^-53, u / sqrt(n_slices)) and u the
+ * precision's unit roundoff (2^-53 FP64, 2^-24 FP32 modes, 2^-16 BF16
+ * split).  Truncation errors of neighbouring slices add coherently (~N u_t)
+ * while rounding errors add like a random walk (~sqrt(N) u), hence the
+ * sqrt(N) in the target.  n_slices >= 1. */
+pm_status pm_taylor_theta(int m, int precision, int64_t n_slices, double *theta_out);
 
-/* The planner's choice for a slice with ||G||_1 = nu: Taylor degree m and
- * squarings s minimising the product count (ties to the smaller s), subject
- * to nu / 2^s <= theta_m and m <= max_degree. */
-pm_status pm_plan_expm(double nu, int precision, int max_degree, int *m_out,
-                       int *s_out);
+/* The planner's choice for a slice with ||G||_1 = nu in a propagation of
+ * n_slices slices: Taylor degree m and squarings s minimising the product
+ * count (ties to the smaller s), subject to nu / 2^s <= theta_m and
+ * m <= max_degree. */
+pm_status pm_plan_expm(double nu, int precision, int max_degree, int64_t n_slices,
+                       int *m_out, int *s_out);
 
 #ifdef __cplusplus
 }

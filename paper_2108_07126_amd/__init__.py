@@ -49,8 +49,9 @@ SIGNATURES = {
                                            ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p]),
     "pm_slice_weights_host": (ctypes.c_int, [ctypes.c_int64, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                              ctypes.c_int, ctypes.c_int64, ctypes.c_void_p]),
-    "pm_taylor_theta": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_double_p]),
-    "pm_plan_expm": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int, _c_int_p, _c_int_p]),
+    "pm_taylor_theta": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _c_double_p]),
+    "pm_plan_expm": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _c_int_p,
+                                    _c_int_p]),
 }
 
 
@@ -120,15 +121,16 @@ def slice_weights_host(samples, dt: float, order: int, slice_index: int) -> np.n
     return w
 
 
-def taylor_theta(m: int, precision: int = PM_FP64) -> float:
+def taylor_theta(m: int, precision: int = PM_FP64, n_slices: int = 1) -> float:
     t = ctypes.c_double()
-    _check(_lib.pm_taylor_theta(m, precision, ctypes.byref(t)))
+    _check(_lib.pm_taylor_theta(m, precision, n_slices, ctypes.byref(t)))
     return t.value
 
 
-def plan_expm(nu: float, precision: int = PM_FP64, max_degree: int = MAX_TAYLOR_DEGREE) -> Tuple[int, int]:
+def plan_expm(nu: float, precision: int = PM_FP64, max_degree: int = MAX_TAYLOR_DEGREE,
+              n_slices: int = 1) -> Tuple[int, int]:
     m, s = ctypes.c_int(), ctypes.c_int()
-    _check(_lib.pm_plan_expm(nu, precision, max_degree, ctypes.byref(m), ctypes.byref(s)))
+    _check(_lib.pm_plan_expm(nu, precision, max_degree, n_slices, ctypes.byref(m), ctypes.byref(s)))
     return m.value, s.value
 
 

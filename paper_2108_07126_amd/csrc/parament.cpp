@@ -38,6 +38,7 @@ struct pm_ctx {
     uint8_t pair_a[pm::kMaxBasis] = {};
     uint8_t pair_b[pm::kMaxBasis] = {};
     double theta[pm::kMaxDeg + 1] = {};
+    int64_t theta_n = -1;        // slice count the theta table was made for
     int max_degree = PM_MAX_TAYLOR_DEGREE;
     int force_s = -1;
     int64_t chunk_override = 0;
@@ -142,8 +143,14 @@ void plan_host(const double* theta, int md, int force_s, double nu, int* m_out, 
     *s_out = bs;
 }
 
-void fill_theta(double* theta, int precision) {
+// Truncation target for a propagation of n slices (see pm_taylor_theta).
+double truncation_target(int precision, int64_t n) {
     const double u = unit_roundoff(precision);
+    return std::max(std::ldexp(1.0, -53), u / std::sqrt((double)std::max<int64_t>(n, 1)));
+}
+
+void fill_theta(double* theta, int precision, int64_t n) {
+    const double u = truncation_target(precision, n);
     theta[0] = 0.0;
     for (int m = 1; m <= pm::kMaxDeg; ++m) theta[m] = taylor_theta(m, u);
 }
@@ -327,6 +334,10 @@ pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double
     p.counters = ctx->d_counters;
     p.U_out = d_U;
     p.h = dt;
+    if (ctx->theta_n != N) {
+        fill_theta(ctx->theta, ctx->precision, N);
+        ctx->theta_n = N;
+    }
     std::memcpy(p.theta, ctx->theta, sizeof(p.theta));
     p.K = (int)ctx->n_ctrl;
     p.M = ctx->M;
@@ -429,20 +440,21 @@ int64_t pm_basis_count(int64_t n_ctrl, int order) {
     return -1;
 }
 
-pm_status pm_taylor_theta(int m, int precision, double* theta_out) {
-    if (m < 1 || m > PM_MAX_TAYLOR_DEGREE || !theta_out) return PM_E_INVALID_ARG;
-    const double u = unit_roundoff(precision);
-    if (u < 0) return PM_E_INVALID_ARG;
-    *theta_out = taylor_theta(m, u);
+pm_status pm_taylor_theta(int m, int precision, int64_t n_slices, double* theta_out) {
+    if (m < 1 || m > PM_MAX_TAYLOR_DEGREE || !theta_out || n_slices < 1) return PM_E_INVALID_ARG;
+    if (unit_roundoff(precision) < 0) return PM_E_INVALID_ARG;
+    *theta_out = taylor_theta(m, truncation_target(precision, n_slices));
     return PM_OK;
 }
 
-pm_status pm_plan_expm(double nu, int precision, int max_degree, int* m_out, int* s_out) {
-    if (!m_out || !s_out || !(nu >= 0.0) || max_degree < 1 || max_degree > PM_MAX_TAYLOR_DEGREE)
+pm_status pm_plan_expm(double nu, int precision, int max_degree, int64_t n_slices, int* m_out,
+                       int* s_out) {
+    if (!m_out || !s_out || !(nu >= 0.0) || max_degree < 1 || max_degree > PM_MAX_TAYLOR_DEGREE ||
+        n_slices < 1)
         return PM_E_INVALID_ARG;
     if (unit_roundoff(precision) < 0) return PM_E_INVALID_ARG;
     double th[pm::kMaxDeg + 1];
-    fill_theta(th, precision);
+    fill_theta(th, precision, n_slices);
     plan_host(th, max_degree, -1, nu, m_out, s_out);
     return PM_OK;
 }
@@ -507,7 +519,6 @@ pm_status pm_create(pm_ctx** out, int device, int precision) {
     if (!ctx) return PM_E_OOM;
     ctx->device = device;
     ctx->precision = precision;
-    fill_theta(ctx->theta, precision);
     *out = ctx;
     return PM_OK;
 }

@@ -96,15 +96,17 @@ def _taylor(X, m):
     return T
 
 
-@pytest.mark.parametrize("prec,u", [(pm.PM_FP64, 2.0 ** -53), (pm.PM_FP32, 2.0 ** -24),
-                                    (pm.PM_BF16_SPLIT, 2.0 ** -16)])
-def test_taylor_theta_bounds_truncation(prec, u):
-    """theta_m makes the remainder bound equal u, and the true truncation error
-    of exp(X) - T_m(X) at ||X||_1 = theta_m (X skew-Hermitian) stays below it."""
+@pytest.mark.parametrize("prec,u,n", [(pm.PM_FP64, 2.0 ** -53, 1), (pm.PM_FP32, 2.0 ** -24, 1),
+                                      (pm.PM_BF16_SPLIT, 2.0 ** -16, 1), (pm.PM_FP32, 2.0 ** -32, 2 ** 16),
+                                      (pm.PM_FP64, 2.0 ** -53, 2 ** 16)])
+def test_taylor_theta_bounds_truncation(prec, u, n):
+    """theta_m makes the remainder bound equal the truncation target
+    max(2^-53, u/sqrt(N)), and the true truncation error of exp(X) - T_m(X) at
+    ||X||_1 = theta_m (X skew-Hermitian) stays below it."""
     rng = np.random.default_rng(4)
     prev = 0.0
     for m in range(1, 22):
-        th = pm.taylor_theta(m, prec)
+        th = pm.taylor_theta(m, prec, n)
         assert th > prev
         prev = th
         bound = th ** (m + 1) / math.factorial(m + 1) / (1 - th / (m + 2))
@@ -123,10 +125,11 @@ def _cost(m):
 
 
 @pytest.mark.parametrize("prec", [pm.PM_FP64, pm.PM_FP32, pm.PM_BF16_SPLIT])
-def test_planner_is_feasible_and_optimal(prec):
-    th = {m: pm.taylor_theta(m, prec) for m in range(1, 22)}
+@pytest.mark.parametrize("n", [1, 4096, 2 ** 17])
+def test_planner_is_feasible_and_optimal(prec, n):
+    th = {m: pm.taylor_theta(m, prec, n) for m in range(1, 22)}
     for nu in [0.0, 1e-9, 3e-4, 0.0043, 0.0346, 0.195, 0.43, 1.0, 3.7, 40.0, 1e4]:
-        m, s = pm.plan_expm(nu, prec)
+        m, s = pm.plan_expm(nu, prec, n_slices=n)
         assert nu / 2 ** s <= th[m]
         # brute force over all feasible (m', s')
         best = min(_cost(mm) + ss for ss in range(0, 40) for mm in th if nu / 2 ** ss <= th[mm])
