@@ -33,6 +33,14 @@ __device__ __forceinline__ double wave_uniform(double x) {
 
 __device__ __forceinline__ int wave_uniform(int x) { return __builtin_amdgcn_readfirstlane(x); }
 
+// Value of x in lane l (l wave-uniform).
+__device__ __forceinline__ double readlane_d(double x, int l) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+    const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
 // Weight of basis matrix m in slice j (the expand step; eq. magnus_coeffs
 // for order 4 with the commutator sign of the standard product order).
 __device__ __forceinline__ double slice_weight(const PropParams& p, int64_t j, int m) {
@@ -64,39 +72,229 @@ __device__ __forceinline__ int taylor_products(int m) {
     return m / 2 + 1;
 }
 
+// Smallest s >= 0 with nu / 2^s <= th (th > 0).
+__device__ __forceinline__ int min_squarings(double nu, double th) {
+    if (!(nu > th)) return 0;
+    int e;
+    (void)frexp(nu / th, &e);          // nu / th in [2^(e-1), 2^e), up to rounding
+    int s = e;
+    if (ldexp(nu, -s) > th) s += 1;
+    else if (s > 0 && ldexp(nu, -(s - 1)) <= th) s -= 1;
+    return s;
+}
+
 // Choose (m, s): minimise taylor_products(m) + s with nu / 2^s <= theta_m,
 // m <= max_degree; ties go to the smaller s.  Degrees 1, 2 and odd m >= 3
-// are the only candidates (an even m >= 4 costs as much as m + 1).
+// are the only candidates (an even m >= 4 costs as much as m + 1).  With
+// force_s >= 0 the smallest feasible degree is taken (max_degree if none).
+// Unrolled over the candidates so the thresholds stay in scalar registers.
 __device__ __forceinline__ void plan_expm(const PropParams& p, double nu, int& m_out, int& s_out) {
+    constexpr int kCand[12] = {1, 2, 3, 5, 7, 9, 11, 13, 15, 17, 19, 21};
     const int md = p.max_degree;
+    int bm = md, bs = 0, bc = 1 << 30;
     if (p.force_s >= 0) {
         const double x = ldexp(nu, -p.force_s);
-        int m = md;
-        for (int c = 1; c <= md; c = (c < 3 ? c + 1 : c + 2)) {
-            if (p.theta[c] >= x) { m = c; break; }
+#pragma unroll
+        for (int i = 11; i >= 0; --i) {
+            const int c = kCand[i];
+            if (c <= md && p.theta[c] >= x) bm = c;
         }
-        m_out = m;
+        m_out = bm;
         s_out = p.force_s;
         return;
     }
-    int best_m = md, best_s = 0, best_cost = 1 << 30;
-    for (int s = 0; s < 64; ++s) {
-        if (s >= best_cost) break;
-        const double x = ldexp(nu, -s);
-        for (int c = 1; c <= md; c = (c < 3 ? c + 1 : c + 2)) {
-            if (p.theta[c] >= x) {
-                const int cost = taylor_products(c) + s;
-                if (cost < best_cost) { best_cost = cost; best_m = c; best_s = s; }
-                break;
+#pragma unroll
+    for (int i = 0; i < 12; ++i) {
+        const int c = kCand[i];
+        if (c <= md) {
+            const int s = min_squarings(nu, p.theta[c]);
+            const int cost = taylor_products(c) + s;
+            if (cost < bc || (cost == bc && s < bs)) {
+                bc = cost;
+                bm = c;
+                bs = s;
             }
         }
     }
-    if (best_cost == (1 << 30)) {  // nu not finite: keep going, result is NaN anyway
-        best_m = md;
-        best_s = 0;
+    m_out = bm;
+    s_out = bs;
+}
+
+// The same plan with the 12 candidate degrees spread over lanes 0..11 (one
+// candidate each, threshold preloaded in `lane_theta`, +inf elsewhere):
+// every lane packs (cost, s, candidate) into an integer key, and the row
+// minimum of the keys is the plan (ties to the smaller s, as above).
+constexpr int kNumCand = 12;
+__device__ __forceinline__ int cand_degree(int i) { return i < 3 ? i + 1 : 2 * i - 1; }
+
+__device__ __forceinline__ double lane_theta_of(const PropParams& p, int lane) {
+    if (lane >= kNumCand || cand_degree(lane) > p.max_degree) return __builtin_inf();
+    return p.theta[cand_degree(lane)];
+}
+
+__device__ __forceinline__ int row16_min_i(int x) {
+    x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x128, 0xF, 0xF, false));
+    x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x124, 0xF, 0xF, false));
+    x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x122, 0xF, 0xF, false));
+    x = min(x, __builtin_amdgcn_update_dpp(0, x, 0x121, 0xF, 0xF, false));
+    return x;
+}
+
+__device__ __forceinline__ void plan_expm_lanes(const PropParams& p, double nu, int lane,
+                                                double lane_theta, int& m_out, int& s_out) {
+    const bool cand = lane_theta < __builtin_inf();
+    int key;
+    if (p.force_s >= 0) {
+        key = (cand && ldexp(nu, -p.force_s) <= lane_theta) ? lane : 1 << 20;
+        key = __builtin_amdgcn_readfirstlane(row16_min_i(key));
+        m_out = key < kNumCand ? cand_degree(key) : p.max_degree;
+        s_out = p.force_s;
+        return;
     }
-    m_out = best_m;
-    s_out = best_s;
+    const int s = min(min_squarings(nu, cand ? lane_theta : 1.0), 63);
+    const int deg = cand_degree(lane);
+    key = cand ? ((taylor_products(deg) + s) << 12) | (s << 5) | lane : 0x7fffffff;
+    key = __builtin_amdgcn_readfirstlane(row16_min_i(key));
+    m_out = cand_degree(key & 31);
+    s_out = (key >> 5) & 63;
+}
+
+// Branch-free form of slice_weight for a lane-dependent basis index m: the
+// lane gathers up to five samples of the slice and combines them with the
+// formula of its basis matrix.  Lanes m >= M get weight 0.
+struct WeightRecipe {
+    int kind;        // 0: H0 (h), 1: order-2 control, 2: Simpson, 3: commutator with H0, 4: pair, 5: none
+    int64_t xa, xb;  // sample offsets of controls a, b (before adding the slice position)
+};
+
+struct SliceSamples {
+    double x0, x1, x2, y0, y2;
+};
+
+__device__ __forceinline__ WeightRecipe weight_recipe(const PropParams& p, int m) {
+    WeightRecipe r;
+    const int K = p.K;
+    const int64_t S = p.n_samples;
+    r.xa = 0;
+    r.xb = 0;
+    if (m >= p.M) {
+        r.kind = 5;
+    } else if (m == 0) {
+        r.kind = 0;
+    } else if (p.order == 2) {
+        r.kind = 1;
+        r.xa = (int64_t)(m - 1) * S;
+    } else if (m <= K) {
+        r.kind = 2;
+        r.xa = (int64_t)(m - 1) * S;
+    } else if (m <= 2 * K) {
+        r.kind = 3;
+        r.xa = (int64_t)(m - 1 - K) * S;
+    } else {
+        r.kind = 4;
+        r.xa = (int64_t)p.pair_a[m] * S;
+        r.xb = (int64_t)p.pair_b[m] * S;
+    }
+    return r;
+}
+
+// Issue the sample loads of slice j (no use of the values here).
+__device__ __forceinline__ SliceSamples gather_samples(const PropParams& p, const WeightRecipe& r, int64_t j) {
+    SliceSamples v{0.0, 0.0, 0.0, 0.0, 0.0};
+    if (p.K == 0) return v;
+    const double* c = p.samples;
+    if (p.order == 2) {
+        v.x0 = c[r.xa + j];
+    } else {
+        const double* a = c + r.xa + 2 * j;
+        const double* b = c + r.xb + 2 * j;
+        v.x0 = a[0];
+        v.x1 = a[1];
+        v.x2 = a[2];
+        v.y0 = b[0];
+        v.y2 = b[2];
+    }
+    return v;
+}
+
+__device__ __forceinline__ double combine_weight(const PropParams& p, const WeightRecipe& r,
+                                                 const SliceSamples& v) {
+    const double h = p.h;
+    const double h2 = h * h * (1.0 / 12.0);
+    const double w1 = h * v.x0;
+    const double w2 = (h * (1.0 / 6.0)) * (v.x0 + 4.0 * v.x1 + v.x2);
+    const double w3 = h2 * (v.x2 - v.x0);
+    const double w4 = h2 * (v.x0 * v.y2 - v.x2 * v.y0);
+    double w = 0.0;
+    w = r.kind == 0 ? h : w;
+    w = r.kind == 1 ? w1 : w;
+    w = r.kind == 2 ? w2 : w;
+    w = r.kind == 3 ? w3 : w;
+    w = r.kind == 4 ? w4 : w;
+    return w;
+}
+
+// DPP row rotation (within each row of 16 lanes) of a double.
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double x) {
+    const long long b = __double_as_longlong(x);
+    const int lo = __builtin_amdgcn_update_dpp(0, (int)(b & 0xffffffffLL), CTRL, 0xF, 0xF, false);
+    const int hi = __builtin_amdgcn_update_dpp(0, (int)(b >> 32), CTRL, 0xF, 0xF, false);
+    return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
+}
+
+// Sum over the 16 lanes of each row (every lane of the row gets the sum).
+__device__ __forceinline__ double row16_sum(double x) {
+    x += dpp_d<0x128>(x);   // row_ror:8
+    x += dpp_d<0x124>(x);   // row_ror:4
+    x += dpp_d<0x122>(x);   // row_ror:2
+    x += dpp_d<0x121>(x);   // row_ror:1
+    return x;
+}
+
+__device__ __forceinline__ double row16_max(double x) {
+    x = fmax(x, dpp_d<0x128>(x));
+    x = fmax(x, dpp_d<0x124>(x));
+    x = fmax(x, dpp_d<0x122>(x));
+    x = fmax(x, dpp_d<0x121>(x));
+    return x;
+}
+
+// Maximum over the four rows of a wave (lanes 0, 16, 32, 48 hold the row
+// values after a row16 reduction); wave-uniform result.
+__device__ __forceinline__ double rows_max(double x) {
+    return fmax(fmax(readlane_d(x, 0), readlane_d(x, 16)), fmax(readlane_d(x, 32), readlane_d(x, 48)));
+}
+
+// Single-precision variants for row sums of entry bounds: the sum of 16
+// non-negative terms in FP32 is within 16 * 2^-24 of exact, the square roots
+// within 2^-22; rows_max_f inflates the result by 2^-16 so it stays an upper
+// bound, and returns it in FP64.
+__device__ __forceinline__ float abs_bound_f(double re, double im) {
+    return __builtin_sqrtf((float)(re * re + im * im));
+}
+
+__device__ __forceinline__ float row16_sum_f(float x) {
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x128, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x124, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x122, 0xF, 0xF, false));
+    x += __int_as_float(__builtin_amdgcn_update_dpp(0, __float_as_int(x), 0x121, 0xF, 0xF, false));
+    return x;
+}
+
+__device__ __forceinline__ double rows_max_f(float x) {
+    const float a = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 0));
+    const float b = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 16));
+    const float c = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 32));
+    const float d = __int_as_float(__builtin_amdgcn_readlane(__float_as_int(x), 48));
+    return (double)fmaxf(fmaxf(a, b), fmaxf(c, d)) * (1.0 + 0x1p-16) + 0x1p-60;
+}
+
+// Upper bound of |re + i im| from a single-precision square root, inflated
+// past its rounding (relative error < 2^-22) so the bound never falls short.
+__device__ __forceinline__ double abs_bound(double re, double im) {
+    const float q = (float)(re * re + im * im);
+    return (double)__builtin_sqrtf(q) * (1.0 + 0x1p-20) + 0x1p-60;
 }
 
 }  // namespace pm

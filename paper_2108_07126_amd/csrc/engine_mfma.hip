@@ -2,11 +2,11 @@
 //
 // One *team* of (D/16)^2 wavefronts runs a chain of consecutive slices; each
 // wave owns one 16x16 output tile of every D x D matrix, held in registers in
-// the accumulator layout of v_mfma_*_16x16x4 (lane 16 g + j holds rows
-// 4 g + r, r = 0..3, of column j).  Per slice the team
-//   1. expands G_j = sum_m w_m B_m in FP64 (weights from the control samples,
-//      basis tiles streamed from HBM/L2 in that same layout),
-//   2. takes ||G_j||_1 in FP64 and plans the Taylor degree m and squarings s,
+// the accumulator layout of v_mfma_*_16x16x4 (lane 16 g + j holds four rows
+// of column j, see crow()).  Per slice the team
+//   1. expands G_j = sum_m w_m B_m in FP64 (lane m gathers the samples of
+//      weight m one slice ahead; basis tiles from LDS or L2 in that layout),
+//   2. bounds ||G_j||_1 and plans the Taylor degree m and squarings s,
 //   3. evaluates exp(-i G) = C(Y) - i G S'(Y), Y = G^2 (cos / sin Taylor
 //      series split by parity: every product is of commuting Hermitian
 //      matrices), then squares s times,
@@ -147,7 +147,9 @@ __device__ __forceinline__ Tile<T> slot_mul(const double* A, const double* B, co
     const T* Aim = Are + G::PLANE;
     const T* Bre = reinterpret_cast<const T*>(B);
     const T* Bim = Bre + G::PLANE;
-    V rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
+    // Re = sum Ar Br + (-Ai) Bi and Im = sum Ar Bi + Ai Br accumulate in two
+    // interleaved chains, so no combine step follows the MFMAs.
+    V acc_re = {0, 0, 0, 0}, acc_im = {0, 0, 0, 0};
     const int arow = (16 * L.TI + L.j) * G::LD;
     const int bcol = 16 * L.TJ + L.j;
 #pragma unroll
@@ -155,45 +157,49 @@ __device__ __forceinline__ Tile<T> slot_mul(const double* A, const double* B, co
         const int k = 4 * kb + L.g;
         const T ar = Are[arow + k], ai = Aim[arow + k];
         const T br = Bre[k * G::LD + bcol], bi = Bim[k * G::LD + bcol];
-        rr = mfma16(ar, br, rr);
-        ii = mfma16(ai, bi, ii);
-        ri = mfma16(ar, bi, ri);
-        ir = mfma16(ai, br, ir);
+        acc_re = mfma16(ar, br, acc_re);
+        acc_im = mfma16(ar, bi, acc_im);
+        acc_re = mfma16(-ai, bi, acc_re);
+        acc_im = mfma16(ai, br, acc_im);
     }
     Tile<T> out;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        out.re[r] = rr[r] - ii[r];
-        out.im[r] = ri[r] + ir[r];
+        out.re[r] = acc_re[r];
+        out.im[r] = acc_im[r];
     }
     return out;
 }
 
-// ||G||_1 (max over columns of sum_i |G_ij|), FP64, same value in every lane.
-template <class G>
+// ||G||_1 of the Hermitian G, taken as its max row sum (equal for Hermitian
+// matrices), FP64 sums of entry bounds; same value in every lane.  A row of a
+// tile lives in the 16 lanes of one lane group (one register), so row sums
+// are DPP rotations; tiles of a row are added through LDS.
+template <class G, typename T>
 __device__ __forceinline__ double team_norm1(const double* gre, const double* gim, const Lane& L,
                                              double* red) {
-    double cs = 0.0;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) cs += sqrt(gre[r] * gre[r] + gim[r] * gim[r]);
-    cs += __shfl_xor(cs, 16);
-    cs += __shfl_xor(cs, 32);
-    double mx;
+    double rs[4];
     if constexpr (G::TW == 1) {
-        mx = cs;
-    } else {
-        if (L.lane < 16) red[L.TI * G::D + 16 * L.TJ + L.lane] = cs;
-        __syncthreads();
-        mx = 0.0;
-        if (L.lane < G::D) {
+        float fs[4];
 #pragma unroll
-            for (int ti = 0; ti < G::TD; ++ti) mx += red[ti * G::D + L.lane];
+        for (int r = 0; r < 4; ++r) fs[r] = row16_sum_f(abs_bound_f(gre[r], gim[r]));
+        return rows_max_f(fmaxf(fmaxf(fs[0], fs[1]), fmaxf(fs[2], fs[3])));
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) rs[r] = row16_sum(abs_bound(gre[r], gim[r]));
+        if (L.j == 0) {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) red[L.TJ * G::D + 16 * L.TI + crow<T>(L.g, r)] = rs[r];
         }
         __syncthreads();
-    }
+        double tot = 0.0;
+        if (L.lane < G::D) {
 #pragma unroll
-    for (int off = 1; off < 64; off <<= 1) mx = fmax(mx, __shfl_xor(mx, off));
-    return mx;
+            for (int tj = 0; tj < G::TD; ++tj) tot += red[tj * G::D + L.lane];
+        }
+        __syncthreads();
+        return rows_max(row16_max(tot));
+    }
 }
 
 // exp(-i G) for a (pre-scaled) Hermitian tile set by the degree-m Taylor
@@ -355,13 +361,22 @@ __device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, c
     }
 }
 
-template <typename T, int D, int NT>
+// Waves per SIMD the register allocation must allow.
+template <typename T, int D>
+constexpr int min_waves_per_eu() {
+    return D == 64 ? 4 : (std::is_same<T, double>::value ? 3 : 4);
+}
+
+template <typename T, int D, int NT, bool BL>
 __global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
+__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, D>(), 8)))
 propagate_mfma(PropParams p) {
     using G = Geo<D, NT>;
-    __shared__ double smem[NT * 2 * G::SLOT];
-    __shared__ double red[G::TD * D];
-    __shared__ int tick;
+    extern __shared__ double dsm[];
+    double* slots = dsm;
+    double* red = slots + NT * 2 * G::SLOT;
+    int* tick = reinterpret_cast<int*>(red + G::TD * D);
+    double* lbasis = red + G::TD * D + 2;
 
     Lane L;
     L.lane = threadIdx.x & 63;
@@ -372,20 +387,37 @@ propagate_mfma(PropParams p) {
     L.wt = wave % G::TW;
     L.TI = L.wt / G::TD;
     L.TJ = L.wt % G::TD;
-    const int64_t leaf = (int64_t)blockIdx.x * NT + team;
-    if (leaf >= p.n_leaves) return;
-    double* s0 = smem + team * 2 * G::SLOT;
+    double* s0 = slots + team * 2 * G::SLOT;
     double* s1 = s0 + G::SLOT;
 
-    const int64_t j0 = leaf * p.chunk;
+    // the block's copy of the basis (same for every slice)
+    if constexpr (BL) {
+        const int n = p.M * G::TW * 512;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
+        __syncthreads();
+    }
+    const double* bas = BL ? lbasis : p.basis;
+
+    // this team's chain of consecutive slices (empty past the end)
+    const int64_t chain = (int64_t)blockIdx.x * NT + team;
+    const int64_t j0 = min(p.n_slices, chain * p.chunk);
     const int64_t j1 = min(p.n_slices, j0 + p.chunk);
     Tile<T> Q = ident<T>(L);
+    // lane m < M gathers and combines the weight of basis matrix m; the next
+    // slice's samples are loaded while this slice is exponentiated
+    const WeightRecipe wr = weight_recipe(p, L.lane);
+    const double lth = lane_theta_of(p, L.lane);
+    SliceSamples smp = gather_samples(p, wr, j0 < j1 ? j0 : 0);
     for (int64_t j = j0; j < j1; ++j) {
+        const double wl = combine_weight(p, wr, smp);
+        if (j + 1 < j1) smp = gather_samples(p, wr, j + 1);
         // expand (FP64)
         double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
+        const int64_t bofs = mfma_basis_index(D, 0, L.TI, L.TJ, 0, 0, L.lane);
+#pragma unroll 4
         for (int m = 0; m < p.M; ++m) {
-            const double w = slice_weight(p, j, m);
-            const double* b = p.basis + mfma_basis_index(D, m, L.TI, L.TJ, 0, 0, L.lane);
+            const double w = readlane_d(wl, m);
+            const double* b = bas + bofs + (int64_t)m * G::TW * 512;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 gre[r] = fma(w, b[r * 64], gre[r]);
@@ -393,9 +425,9 @@ propagate_mfma(PropParams p) {
             }
         }
         // plan (FP64)
-        const double nu = wave_uniform(team_norm1<G>(gre, gim, L, red));
+        const double nu = wave_uniform(team_norm1<G, T>(gre, gim, L, red));
         int m, s;
-        plan_expm(p, nu, m, s);
+        plan_expm_lanes(p, nu, L.lane, lth, m, s);
         m = wave_uniform(m);
         s = wave_uniform(s);
         Tile<T> Gt;
@@ -421,16 +453,49 @@ propagate_mfma(PropParams p) {
         team_sync<G>();
         Q = slot_mul<G, T>(s0, s1, L);
     }
-    tree_reduce<G>(p, leaf, relayout<G, double>(Q, s0, L), L, s0, s1, &tick);
+    Tile<double> Qd = relayout<G, double>(Q, s0, L);
+    // one-wave teams of a block: combine their chains in LDS (later team on
+    // the left), so the block enters the global tree as a single leaf
+    if constexpr (NT > 1) {
+        for (int st = 1; st < NT; st <<= 1) {
+            __syncthreads();
+            slot_store<G, double>(s1, Qd, L);
+            __syncthreads();
+            if ((team & (2 * st - 1)) == 0) {
+                const double* later = slots + (team + st) * 2 * G::SLOT + G::SLOT;
+                Qd = slot_mul<G, double>(later, s1, L);
+            }
+        }
+        if (team != 0) return;
+    }
+    tree_reduce<G>(p, blockIdx.x, Qd, L, s0, s1, tick);
+}
+
+template <int D, int NT>
+constexpr size_t lds_fixed_bytes() {
+    using G = Geo<D, NT>;
+    return sizeof(double) * ((size_t)NT * 2 * G::SLOT + (size_t)G::TD * D + 2);
+}
+
+template <typename T, int D, int NT, bool BL>
+hipError_t launch_one(const PropParams& p, hipStream_t stream) {
+    using G = Geo<D, NT>;
+    const size_t lds = lds_fixed_bytes<D, NT>() + (BL ? sizeof(double) * (size_t)p.M * G::TW * 512 : 0);
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)propagate_mfma<T, D, NT, BL>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    hipLaunchKernelGGL((propagate_mfma<T, D, NT, BL>), dim3((unsigned)p.n_leaves), dim3(G::THREADS), lds,
+                       stream, p);
+    return hipGetLastError();
 }
 
 template <typename T, int D, int NT>
-hipError_t launch_one(const PropParams& p, hipStream_t stream) {
-    using G = Geo<D, NT>;
-    const int64_t blocks = (p.n_leaves + NT - 1) / NT;
-    hipLaunchKernelGGL((propagate_mfma<T, D, NT>), dim3((unsigned)blocks), dim3(G::THREADS), 0,
-                       stream, p);
-    return hipGetLastError();
+hipError_t launch_bl(const PropParams& p, hipStream_t stream) {
+    return p.basis_lds ? launch_one<T, D, NT, true>(p, stream) : launch_one<T, D, NT, false>(p, stream);
 }
 
 }  // namespace
@@ -440,13 +505,13 @@ constexpr int kNT16 = 4;
 
 hipError_t launch_mfma(int D, bool fp64, const PropParams& p, hipStream_t stream) {
     switch (D) {
-        case 16: return fp64 ? launch_one<double, 16, kNT16>(p, stream) : launch_one<float, 16, kNT16>(p, stream);
-        case 32: return fp64 ? launch_one<double, 32, 1>(p, stream) : launch_one<float, 32, 1>(p, stream);
-        case 64: return fp64 ? launch_one<double, 64, 1>(p, stream) : launch_one<float, 64, 1>(p, stream);
+        case 16: return fp64 ? launch_bl<double, 16, kNT16>(p, stream) : launch_bl<float, 16, kNT16>(p, stream);
+        case 32: return fp64 ? launch_bl<double, 32, 1>(p, stream) : launch_bl<float, 32, 1>(p, stream);
+        case 64: return fp64 ? launch_bl<double, 64, 1>(p, stream) : launch_bl<float, 64, 1>(p, stream);
         default: return hipErrorInvalidValue;
     }
 }
 
-int mfma_leaves_per_block(int D) { return D == 16 ? kNT16 : 1; }
+int mfma_chains_per_block(int D) { return D == 16 ? kNT16 : 1; }
 
 }  // namespace pm

@@ -18,7 +18,7 @@
 namespace pm {
 hipError_t launch_mfma(int D, bool fp64, const PropParams& p, hipStream_t stream);
 hipError_t launch_valu(int D, bool fp64, const PropParams& p, hipStream_t stream);
-int mfma_leaves_per_block(int D);
+int mfma_chains_per_block(int D);
 }  // namespace pm
 
 using cplx = std::complex<double>;
@@ -298,11 +298,12 @@ pm_status check_prop_args(pm_ctx* ctx, int64_t n_samples, double dt) {
     return PM_OK;
 }
 
+// Chain length: about one chain per resident wave team, in whole units.
 int64_t auto_chunk(const pm::EngineInfo& e, int64_t N) {
-    const int64_t target = 2 * (int64_t)e.resident_leaves;
+    const int64_t target = (int64_t)e.resident_chains;
     int64_t c = (N + target - 1) / target;
     if (c < 1) c = 1;
-    const int64_t u = e.leaf_slices_unit;
+    const int64_t u = e.chunk_unit;
     return ((c + u - 1) / u) * u;
 }
 
@@ -311,8 +312,9 @@ pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double
     const pm::EngineInfo& e = ctx->eng;
     const int64_t N = n_slices_of(ctx->order, n_samples);
     int64_t chunk = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N);
-    chunk = ((chunk + e.leaf_slices_unit - 1) / e.leaf_slices_unit) * e.leaf_slices_unit;
-    const int64_t leaves = (N + chunk - 1) / chunk;
+    chunk = ((chunk + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
+    const int64_t chains = (N + chunk - 1) / chunk;
+    const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
     const size_t node_bytes = (size_t)e.D * e.D * 16;
     pm_status st = ensure(ctx, (void**)&ctx->d_nodes, &ctx->nodes_bytes,
                           node_bytes * (size_t)(2 * leaves + 64), "tree nodes");
@@ -328,6 +330,7 @@ pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double
     p.n_samples = n_samples;
     p.n_slices = N;
     p.chunk = chunk;
+    p.n_chains = chains;
     p.n_leaves = leaves;
     p.slices_out = d_slices;
     p.nodes = ctx->d_nodes;
@@ -345,6 +348,9 @@ pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double
     p.du = (int)ctx->dim;
     p.max_degree = ctx->max_degree;
     p.force_s = ctx->force_s;
+    // D = 16: the block keeps the basis in LDS when it is small (<= 64 KiB)
+    p.basis_lds = (e.kind == pm::ENGINE_MFMA && e.D == 16 &&
+                   (size_t)ctx->M * e.D * e.D * 16 <= 64 * 1024) ? 1 : 0;
     std::memcpy(p.pair_a, ctx->pair_a, sizeof(p.pair_a));
     std::memcpy(p.pair_b, ctx->pair_b, sizeof(p.pair_b));
     hipError_t he = pm::launch_propagate(e, ctx->precision, p, stream);
@@ -363,15 +369,15 @@ bool pick_engine(int du, int precision, EngineInfo* out) {
     if (du <= 4) {
         e.kind = ENGINE_VALU;
         e.D = du <= 2 ? 2 : 4;
-        e.leaf_slices_unit = 64;
-        e.leaves_per_block = 4;
-        e.resident_leaves = 256 * 8;
+        e.chunk_unit = 64;          // one slice run per lane
+        e.chains_per_leaf = 1;      // a wave is a leaf
+        e.resident_chains = 256 * 8;
     } else {
         e.kind = ENGINE_MFMA;
         e.D = du <= 16 ? 16 : (du <= 32 ? 32 : 64);
-        e.leaf_slices_unit = 1;
-        e.leaves_per_block = mfma_leaves_per_block(e.D);
-        e.resident_leaves = e.D == 16 ? 256 * 8 : (e.D == 32 ? 256 * 4 : 256);
+        e.chunk_unit = 1;
+        e.chains_per_leaf = mfma_chains_per_block(e.D);   // a block is a leaf
+        e.resident_chains = e.D == 16 ? 256 * 8 : (e.D == 32 ? 256 * 4 : 256);
         e.f64_rows = precision == PM_FP64 ? 1 : 0;
     }
     *out = e;

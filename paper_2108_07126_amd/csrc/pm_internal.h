@@ -20,8 +20,9 @@ struct PropParams {
     const double* samples;    // [K][n_samples]
     int64_t n_samples;
     int64_t n_slices;         // N
-    int64_t chunk;            // consecutive slices per leaf
-    int64_t n_leaves;         // ceil(N / chunk)
+    int64_t chunk;            // consecutive slices per chain
+    int64_t n_chains;         // ceil(N / chunk)
+    int64_t n_leaves;         // leaves of the product tree (blocks or waves)
     void* slices_out;         // nullptr or [N][du][du] complex (c128 / c64)
     double* nodes;            // tree nodes, [2 * n_leaves][D][D] complex128
     unsigned* counters;       // [2 * n_leaves] pair tickets, zero between launches
@@ -30,6 +31,7 @@ struct PropParams {
     double theta[kMaxDeg + 1];   // Taylor thresholds for the working precision
     int K, M, order, du;
     int max_degree, force_s;
+    int basis_lds;               // MFMA engine: block keeps a copy of the basis in LDS
     uint8_t pair_a[kMaxBasis];   // order 4: control indices of i[H_a, H_b]
     uint8_t pair_b[kMaxBasis];
 };
@@ -43,9 +45,9 @@ enum EngineKind { ENGINE_VALU = 0, ENGINE_MFMA = 1 };
 struct EngineInfo {
     int kind;
     int D;                 // engine dimension
-    int leaf_slices_unit;  // a leaf's chunk is a multiple of this
-    int leaves_per_block;  // teams (MFMA) or waves (VALU) per block
-    int resident_leaves;   // leaves the whole GPU runs at once (rough)
+    int chunk_unit;        // a chain's length is a multiple of this
+    int chains_per_leaf;   // chains combined before the global tree
+    int resident_chains;   // chains the whole GPU runs at once (rough)
     int f64_rows;          // MFMA: accumulator rows interleaved as in FP64 (g + 4r)
 };
 
