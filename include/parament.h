@@ -115,6 +115,31 @@ pm_status pm_equiprop_dev(pm_ctx *ctx, const double *samples_dev,
                           int64_t n_samples, double dt, double *U_out_dev,
                           void *slices_out_dev, void *stream);
 
+/* Adjoint gradient (the paper's outlook on GRAPE-style optimal control,
+ * Applications and outlook section).  For a real loss L of U(T) with
+ * dL = Re Tr(W^H dU(T)) -- W is 2 dL/d conj(U), the convention of PyTorch's
+ * complex gradients -- writes dL/d samples into grad_dev (float64
+ * [n_ctrl][n_samples]).  Runs its own forward pass (U(T) also copied to
+ * U_out_dev when non-NULL, complex128 [dim][dim]) keeping one checkpoint
+ * product per chain of consecutive slices (see pm_set_chunk) and the product
+ * tree's nodes, then a backward pass that recomputes each chain's slice
+ * propagators from its checkpoint and contracts the Frechet derivatives of
+ * exp(-i G_j) with the basis (the chain rule through the expand step's
+ * weights gives the sample gradient).  W_dev: device complex128 [dim][dim].
+ * Enqueued on `stream`; PM_FP64 contexts only (PM_E_UNSUPPORTED otherwise). */
+pm_status pm_backward_dev(pm_ctx *ctx, const double *samples_dev, int64_t n_samples,
+                          double dt, const double *W_dev, double *grad_dev,
+                          double *U_out_dev, void *stream);
+
+/* Gate-fidelity loss and its gradient with host buffers (synchronous):
+ * L = 1 - |Tr(V^H U(T))|^2 / dim^2 for the target V (host complex128
+ * [dim][dim]); *loss receives L, grad (host float64 [n_ctrl][n_samples])
+ * dL/d samples, U_out (NULL or host complex128 [dim][dim]) U(T).  PM_FP64
+ * contexts only. */
+pm_status pm_fidelity_grad(pm_ctx *ctx, const double *samples, int64_t n_samples,
+                           double dt, const double *V, double *loss, double *grad,
+                           double *U_out);
+
 /* Numerics helpers (PARAMENT library section: e.g. a different maximum
  * degree).  max_taylor_degree in [1, PM_MAX_TAYLOR_DEGREE] caps the degree
  * the planner may pick (default PM_MAX_TAYLOR_DEGREE); force_s >= 0 fixes the

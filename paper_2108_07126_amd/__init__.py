@@ -40,6 +40,10 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "pm_equiprop_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_backward_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                       ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_fidelity_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                        ctypes.c_void_p, _c_double_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pm_set_expm_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "pm_set_chunk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -220,6 +224,77 @@ class Context:
                                     ctypes.c_void_p(U_t.data_ptr()),
                                     ctypes.c_void_p(slices_t.data_ptr()) if slices_t is not None else None,
                                     ctypes.c_void_p(stream.cuda_stream)), self._h)
+
+
+    def fidelity_grad(self, samples, dt: float, V):
+        """Gate-fidelity loss 1 - |Tr(V^H U)|^2/d^2, its gradient w.r.t. the
+        samples [n_ctrl][n_samples], and U(T).  FP64 contexts only."""
+        s = np.ascontiguousarray(np.asarray(samples, np.float64))
+        if s.ndim == 1:
+            s = s[None]
+        V = _as_c128(V)
+        loss = ctypes.c_double()
+        grad = np.zeros_like(s)
+        U = np.zeros((self.dim, self.dim), np.complex128)
+        _check(_lib.pm_fidelity_grad(self._h, _ptr(s), s.shape[1], float(dt), _ptr(V), ctypes.byref(loss),
+                                     _ptr(grad), _ptr(U)), self._h)
+        return loss.value, grad, U
+
+    def backward_dev(self, samples_t, dt: float, W_t, grad_t, U_t=None, stream=None):
+        """dL/d samples into grad_t for dL = Re Tr(W^H dU(T)) (device tensors;
+        enqueued on `stream`, default torch's current stream)."""
+        import torch
+        assert samples_t.is_cuda and samples_t.dtype == torch.float64 and samples_t.is_contiguous()
+        assert W_t.is_cuda and W_t.dtype == torch.complex128 and W_t.is_contiguous()
+        assert grad_t.is_cuda and grad_t.dtype == torch.float64 and grad_t.is_contiguous()
+        if stream is None:
+            stream = torch.cuda.current_stream(W_t.device)
+        _check(_lib.pm_backward_dev(self._h, ctypes.c_void_p(samples_t.data_ptr()), samples_t.shape[-1],
+                                    float(dt), ctypes.c_void_p(W_t.data_ptr()),
+                                    ctypes.c_void_p(grad_t.data_ptr()),
+                                    ctypes.c_void_p(U_t.data_ptr()) if U_t is not None else None,
+                                    ctypes.c_void_p(stream.cuda_stream)), self._h)
+
+
+def _make_function():
+    import torch
+
+    class Propagate(torch.autograd.Function):
+        """U(T) = equiprop(samples) with the adjoint backward of the library.
+
+        forward(ctx_obj, samples [n_ctrl][n_samples] float64 cuda, dt) ->
+        U(T) complex128 [dim][dim]; backward turns dL/dconj(U) into dL/d samples
+        through pm_backward_dev."""
+
+        @staticmethod
+        def forward(fctx, pctx, samples, dt):
+            samples = samples.contiguous()
+            U = torch.zeros((pctx.dim, pctx.dim), dtype=torch.complex128, device=samples.device)
+            pctx.equiprop_dev(samples, dt, U)
+            fctx.pctx = pctx
+            fctx.dt = dt
+            fctx.save_for_backward(samples)
+            return U
+
+        @staticmethod
+        def backward(fctx, grad_U):
+            (samples,) = fctx.saved_tensors
+            grad = torch.zeros_like(samples)
+            fctx.pctx.backward_dev(samples, fctx.dt, grad_U.contiguous().to(torch.complex128), grad)
+            return None, grad, None
+
+    return Propagate
+
+
+_Propagate = None
+
+
+def propagate_autograd(pctx: "Context", samples_t, dt: float):
+    """Differentiable U(T) (torch.autograd) through the library's adjoint."""
+    global _Propagate
+    if _Propagate is None:
+        _Propagate = _make_function()
+    return _Propagate.apply(pctx, samples_t, dt)
 
 
 def propagate(H0, Hk, samples, dt: float, order: int = 2, precision: int = PM_FP64,

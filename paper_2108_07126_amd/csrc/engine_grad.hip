@@ -1,0 +1,427 @@
+// Adjoint gradient of a real loss L(U(T)) with respect to every control
+// sample, on the MFMA tile engine in FP64.
+//
+// With W the loss gradient in the convention dL = Re Tr(W^H dU(T)),
+// P_j = U_{j-1} ... U_0 and S_j = U_{N-1} ... U_{j+1}:
+//     dL = Re sum_j Tr(W^H S_j dU_j P_j) = Re sum_j Tr(F_j dG_j),
+//     F_j = L_f(G_j, Lambda_j),  Lambda_j = P_j W^H S_j,  f(G) = exp(-i G),
+// (cyclic trace and Tr(A L_f(G, E)) = Tr(L_f(G, A) E)), so that
+//     dL / dw_{j,m} = Re Tr(F_j B_m)
+// for the expand step's weights; the chain rule through the weight formulas
+// gives dL / d samples.  The prefix/suffix structure is carried by
+//     Omega_j = P_j W^H (U_{N-1} ... U_j),  Lambda_j = Omega_j U_j^H,
+//     Omega_{j+1} = U_j Omega_j U_j^H,
+// started at each chain from its checkpoint P_{j0}: the forward pass (run
+// just before, with every tree node kept) leaves the product of every aligned
+// power-of-two range of blocks, and P_{j0} is assembled from at most
+// log2(#blocks) of them plus the earlier chains of its own block; then
+// Omega_{j0} = P Z P^H with Z = W^H U(T) (P unitary).  Inside a chain the
+// slices are recomputed (a checkpoint every `chunk` slices, nothing else
+// stored).  F_j is the upper-right block of exp(-i [[G, Lambda], [0, G]]),
+// evaluated with the same cos/sin Taylor scheme and scaling-and-squaring as
+// the forward pass on (value, derivative) pairs:
+//     (A, dA)(B, dB) = (A B, A dB + dA B).
+#include "mfma_tiles.h"
+
+namespace pm {
+namespace {
+
+template <class G>
+__device__ __forceinline__ Tile<double> load_user(const double* A, int du, double pad_diag,
+                                                  const Lane& L) {
+    Tile<double> t;
+    const int col = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        if (row < du && col < du) {
+            t.re[r] = A[(row * du + col) * 2 + 0];
+            t.im[r] = A[(row * du + col) * 2 + 1];
+        } else {
+            t.re[r] = (row == col) ? pad_diag : 0.0;
+            t.im[r] = 0.0;
+        }
+    }
+    return t;
+}
+
+// The conjugate transpose of a tile set, stored into a slot.
+template <class G>
+__device__ __forceinline__ void slot_store_adj(double* slot, const Tile<double>& t, const Lane& L) {
+    double* re = slot;
+    double* im = slot + G::PLANE;
+    const int col = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        re[col * G::LD + row] = t.re[r];
+        im[col * G::LD + row] = -t.im[r];
+    }
+}
+
+__device__ __forceinline__ Tile<double> tadd(const Tile<double>& a, const Tile<double>& b) {
+    Tile<double> c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        c.re[r] = a.re[r] + b.re[r];
+        c.im[r] = a.im[r] + b.im[r];
+    }
+    return c;
+}
+
+__device__ __forceinline__ Tile<double> tzero() {
+    Tile<double> c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) c.re[r] = c.im[r] = 0.0;
+    return c;
+}
+
+__device__ __forceinline__ Tile<double> tscale(const Tile<double>& a, int e) {
+    Tile<double> c;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        c.re[r] = ldexp(a.re[r], e);
+        c.im[r] = ldexp(a.im[r], e);
+    }
+    return c;
+}
+
+// C - i S
+__device__ __forceinline__ Tile<double> c_minus_is(const Tile<double>& C, const Tile<double>& S) {
+    Tile<double> u;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        u.re[r] = C.re[r] + S.im[r];
+        u.im[r] = C.im[r] - S.re[r];
+    }
+    return u;
+}
+
+template <class G>
+__device__ __forceinline__ Tile<double> mul2(const Tile<double>& A, const Tile<double>& B,
+                                             const Lane& L, double* s0, double* s1) {
+    team_sync<G>();
+    slot_store<G, double>(s0, A, L);
+    slot_store<G, double>(s1, B, L);
+    team_sync<G>();
+    return slot_mul<G, double>(s0, s1, L);
+}
+
+// A B^H
+template <class G>
+__device__ __forceinline__ Tile<double> mul_adjB(const Tile<double>& A, const Tile<double>& B,
+                                                 const Lane& L, double* s0, double* s1) {
+    team_sync<G>();
+    slot_store<G, double>(s0, A, L);
+    slot_store_adj<G>(s1, B, L);
+    team_sync<G>();
+    return slot_mul<G, double>(s0, s1, L);
+}
+
+// A^H B
+template <class G>
+__device__ __forceinline__ Tile<double> mul_adjA(const Tile<double>& A, const Tile<double>& B,
+                                                 const Lane& L, double* s0, double* s1) {
+    team_sync<G>();
+    slot_store_adj<G>(s0, A, L);
+    slot_store<G, double>(s1, B, L);
+    team_sync<G>();
+    return slot_mul<G, double>(s0, s1, L);
+}
+
+// (exp(-i G), L_f(G, E)) by the degree-m cos/sin Taylor scheme on
+// (value, derivative) pairs; G and E pre-scaled by 2^-s.
+template <class G>
+__device__ void pair_taylor(const Tile<double>& Gt, const Tile<double>& Et, int m, const Lane& L,
+                            double* s0, double* s1, Tile<double>& U, Tile<double>& dU) {
+    Tile<double> C = ident<double>(L), dC = tzero(), S, dS;
+    if (m <= 1) {
+        S = Gt;
+        dS = Et;
+    } else {
+        const int qc = m / 2, qs = (m - 1) / 2;
+        team_sync<G>();
+        slot_store<G, double>(s0, Gt, L);
+        slot_store<G, double>(s1, Et, L);
+        team_sync<G>();
+        const Tile<double> Y = slot_mul<G, double>(s0, s0, L);
+        const Tile<double> dY = tadd(slot_mul<G, double>(s0, s1, L), slot_mul<G, double>(s1, s0, L));
+        Tile<double> Sp = ident<double>(L), dSp = tzero();
+        axpy(C, cos_coef(1), Y);
+        axpy(dC, cos_coef(1), dY);
+        if (qs >= 1) {
+            axpy(Sp, sin_coef(1), Y);
+            axpy(dSp, sin_coef(1), dY);
+        }
+        Tile<double> P = Y, dP = dY;
+        for (int k = 2; k <= qc; ++k) {
+            team_sync<G>();
+            slot_store<G, double>(s0, P, L);
+            slot_store<G, double>(s1, Y, L);
+            team_sync<G>();
+            const Tile<double> Pn = slot_mul<G, double>(s0, s1, L);
+            team_sync<G>();
+            slot_store<G, double>(s1, dY, L);
+            team_sync<G>();
+            const Tile<double> t1 = slot_mul<G, double>(s0, s1, L);   // P dY
+            team_sync<G>();
+            slot_store<G, double>(s0, dP, L);
+            slot_store<G, double>(s1, Y, L);
+            team_sync<G>();
+            const Tile<double> t2 = slot_mul<G, double>(s0, s1, L);   // dP Y
+            P = Pn;
+            dP = tadd(t1, t2);
+            axpy(C, cos_coef(k), P);
+            axpy(dC, cos_coef(k), dP);
+            if (k <= qs) {
+                axpy(Sp, sin_coef(k), P);
+                axpy(dSp, sin_coef(k), dP);
+            }
+        }
+        if (qs >= 1) {
+            team_sync<G>();
+            slot_store<G, double>(s0, Gt, L);
+            slot_store<G, double>(s1, Sp, L);
+            team_sync<G>();
+            S = slot_mul<G, double>(s0, s1, L);
+            team_sync<G>();
+            slot_store<G, double>(s1, dSp, L);
+            team_sync<G>();
+            const Tile<double> t1 = slot_mul<G, double>(s0, s1, L);   // G dS'
+            team_sync<G>();
+            slot_store<G, double>(s0, Et, L);
+            slot_store<G, double>(s1, Sp, L);
+            team_sync<G>();
+            const Tile<double> t2 = slot_mul<G, double>(s0, s1, L);   // E S'
+            dS = tadd(t1, t2);
+        } else {
+            S = Gt;
+            dS = Et;
+        }
+    }
+    U = c_minus_is(C, S);
+    dU = c_minus_is(dC, dS);
+}
+
+// Sum over the team of a per-lane value; uniform result.  red: LDS, TW doubles.
+template <class G>
+__device__ __forceinline__ double team_sum(double x, const Lane& L, double* red) {
+    x = row16_sum(x);
+    x = readlane_d(x, 0) + readlane_d(x, 16) + readlane_d(x, 32) + readlane_d(x, 48);
+    if constexpr (G::TW == 1) {
+        return x;
+    } else {
+        __syncthreads();
+        if (L.lane == 0) red[L.wt] = x;
+        __syncthreads();
+        double t = 0.0;
+#pragma unroll
+        for (int w = 0; w < G::TW; ++w) t += red[w];
+        return t;
+    }
+}
+
+template <int D, int NT, bool BL>
+__global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
+__attribute__((amdgpu_waves_per_eu(D == 64 ? 4 : 2, 8)))
+backward_mfma(GradParams gp) {
+    using G = Geo<D, NT>;
+    const PropParams& p = gp.p;
+    extern __shared__ double dsm[];
+    double* slots = dsm;
+    double* red = slots + NT * 2 * G::SLOT;
+    double* lbasis = red + G::TD * D + 2;
+
+    Lane L;
+    L.lane = threadIdx.x & 63;
+    L.g = L.lane >> 4;
+    L.j = L.lane & 15;
+    const int wave = wave_uniform((int)(threadIdx.x >> 6));
+    const int team = wave / G::TW;
+    L.wt = wave % G::TW;
+    L.TI = L.wt / G::TD;
+    L.TJ = L.wt % G::TD;
+    double* s0 = slots + team * 2 * G::SLOT;
+    double* s1 = s0 + G::SLOT;
+    if constexpr (BL) {
+        const int n = p.M * G::TW * 512;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
+        __syncthreads();
+    }
+    const double* bas = BL ? lbasis : p.basis;
+    const int64_t chain = (int64_t)blockIdx.x * NT + team;
+    if (chain >= p.n_chains) return;   // no block-wide barrier follows
+    const int64_t j0 = chain * p.chunk;
+    const int64_t j1 = min(p.n_slices, j0 + p.chunk);
+    const int64_t NN = (int64_t)D * D * 2;
+
+    // checkpoint P = U_{j0-1} ... U_0: aligned tree nodes over the blocks
+    // before this one (earliest range first), then this block's earlier chains
+    Tile<double> P = ident<double>(L);
+    {
+        const int64_t b = blockIdx.x;
+        int nlev = 0;
+        for (int64_t cnt = p.n_leaves; cnt > 1; cnt = (cnt + 1) >> 1) ++nlev;
+        for (int l = nlev; l >= 0; --l) {
+            if ((b >> l) & 1) {
+                int64_t off = 0, cnt = p.n_leaves;
+                for (int q = 0; q < l; ++q) {
+                    off += cnt;
+                    cnt = (cnt + 1) >> 1;
+                }
+                const Tile<double> nd = node_load<G>(p.nodes + (off + (b >> l) - 1) * NN, L);
+                P = mul2<G>(nd, P, L, s0, s1);
+            }
+        }
+        for (int64_t c = b * NT; c < chain; ++c)
+            P = mul2<G>(node_load<G>(p.chain_out + c * NN, L), P, L, s0, s1);
+    }
+    // Omega_{j0} = P Z P^H, Z = W^H U(T)
+    const Tile<double> Wt = load_user<G>(gp.W, p.du, 0.0, L);
+    const Tile<double> UTt = load_user<G>(gp.UT, p.du, 1.0, L);
+    const Tile<double> Z = mul_adjA<G>(Wt, UTt, L, s0, s1);
+    Tile<double> Om = mul_adjB<G>(mul2<G>(P, Z, L, s0, s1), P, L, s0, s1);
+
+    const WeightRecipe wr = weight_recipe(p, L.lane);
+    const double lth = lane_theta_of(p, L.lane);
+    SliceSamples smp = gather_samples(p, wr, j0);
+    const int64_t bofs = mfma_basis_index(D, 0, L.TI, L.TJ, 0, 0, L.lane);
+    for (int64_t j = j0; j < j1; ++j) {
+        const double wl = combine_weight(p, wr, smp);
+        if (j + 1 < j1) smp = gather_samples(p, wr, j + 1);
+        double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
+#pragma unroll 4
+        for (int m = 0; m < p.M; ++m) {
+            const double w = readlane_d(wl, m);
+            const double* bb = bas + bofs + (int64_t)m * G::TW * 512;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                gre[r] = fma(w, bb[r * 64], gre[r]);
+                gim[r] = fma(w, bb[256 + r * 64], gim[r]);
+            }
+        }
+        const double nu = wave_uniform(team_norm1<G, double>(gre, gim, L, red));
+        int m, s;
+        plan_expm_lanes(p, nu, L.lane, lth, m, s);
+        m = wave_uniform(m);
+        s = wave_uniform(s);
+        Tile<double> Gt;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Gt.re[r] = ldexp(gre[r], -s);
+            Gt.im[r] = ldexp(gim[r], -s);
+        }
+        // U_j and Lambda_j = Omega_j U_j^H
+        Tile<double> U = square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
+        const Tile<double> Lam = mul_adjB<G>(Om, U, L, s0, s1);
+        // F_j = L_f(G_j, Lambda_j)
+        Tile<double> Up, F;
+        pair_taylor<G>(Gt, tscale(Lam, -s), m, L, s0, s1, Up, F);
+        for (int q = 0; q < s; ++q) {
+            team_sync<G>();
+            slot_store<G, double>(s0, Up, L);
+            slot_store<G, double>(s1, F, L);
+            team_sync<G>();
+            const Tile<double> Un = slot_mul<G, double>(s0, s0, L);
+            F = tadd(slot_mul<G, double>(s0, s1, L), slot_mul<G, double>(s1, s0, L));
+            Up = Un;
+        }
+        // dL/dw_{j,m} = Re Tr(F B_m) = sum over entries of Re(F) Re(B) + Im(F) Im(B) (B Hermitian)
+        for (int mm = 0; mm < p.M; ++mm) {
+            const double* bb = bas + bofs + (int64_t)mm * G::TW * 512;
+            double part = 0.0;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) part = fma(F.re[r], bb[r * 64], fma(F.im[r], bb[256 + r * 64], part));
+            const double g = team_sum<G>(part, L, red);
+            if (L.lane == 0 && L.wt == 0) gp.gw[j * p.M + mm] = g;
+        }
+        // Omega_{j+1} = U_j Omega_j U_j^H
+        Om = mul_adjB<G>(mul2<G>(U, Om, L, s0, s1), U, L, s0, s1);
+    }
+}
+
+// dL/d samples from dL/dw by the weight formulas of the expand step; one
+// thread per (control, sample).
+__global__ void __launch_bounds__(256) samples_grad(GradParams gp, double* grad) {
+    const PropParams& p = gp.p;
+    const int64_t idx = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+    const int K = p.K, M = p.M;
+    const int64_t S = p.n_samples, N = p.n_slices;
+    if (idx >= (int64_t)K * S) return;
+    const int k = (int)(idx / S);
+    const int64_t q = idx % S;
+    const double h = p.h, h2 = h * h * (1.0 / 12.0);
+    const double* g = gp.gw;
+    const double* c = p.samples;
+    if (p.order == 2) {
+        grad[idx] = h * g[q * M + 1 + k];
+        return;
+    }
+    double acc = 0.0;
+    // role 1 (middle sample of slice (q-1)/2)
+    if (q & 1) {
+        const int64_t j = (q - 1) / 2;
+        acc += (4.0 * h / 6.0) * g[j * M + 1 + k];
+    } else {
+        // role 0 of slice q/2 and role 2 of slice q/2 - 1
+        for (int role = 0; role < 2; ++role) {
+            const int64_t j = role == 0 ? q / 2 : q / 2 - 1;
+            if (j < 0 || j >= N) continue;
+            const double* gj = g + j * M;
+            const double sg = role == 0 ? -1.0 : 1.0;   // d(s2 - s0)
+            acc += (h / 6.0) * gj[1 + k] + sg * h2 * gj[1 + K + k];
+            int mq = 1 + 2 * K;
+            for (int a = 0; a < K; ++a)
+                for (int b = a + 1; b < K; ++b, ++mq) {
+                    // w = h2 (s0_a s2_b - s2_a s0_b)
+                    const double* ca = c + (int64_t)a * S + 2 * j;
+                    const double* cb = c + (int64_t)b * S + 2 * j;
+                    if (a == k) acc += gj[mq] * h2 * (role == 0 ? cb[2] : -cb[0]);
+                    if (b == k) acc += gj[mq] * h2 * (role == 0 ? -ca[2] : ca[0]);
+                }
+        }
+    }
+    grad[idx] = acc;
+}
+
+template <int D, int NT, bool BL>
+hipError_t launch_bwd(const GradParams& gp, size_t lds, hipStream_t stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)backward_mfma<D, NT, BL>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int64_t blocks = (gp.p.n_chains + NT - 1) / NT;
+    hipLaunchKernelGGL((backward_mfma<D, NT, BL>), dim3((unsigned)blocks), dim3(64 * (D / 16) * (D / 16) * NT),
+                       lds, stream, gp);
+    return hipGetLastError();
+}
+
+}  // namespace
+
+int mfma_chains_per_block(int D);
+
+hipError_t launch_backward(int D, const GradParams& gp, double* grad_samples, hipStream_t stream) {
+    const int NT = mfma_chains_per_block(D);
+    const int TD = D / 16;
+    size_t lds = sizeof(double) * ((size_t)NT * 2 * 2 * D * (D + 1) + (size_t)TD * D + 2);
+    const bool bl = gp.p.basis_lds != 0;
+    if (bl) lds += sizeof(double) * (size_t)gp.p.M * TD * TD * 512;
+    hipError_t e;
+    switch (D) {
+        case 16: e = bl ? launch_bwd<16, 4, true>(gp, lds, stream) : launch_bwd<16, 4, false>(gp, lds, stream); break;
+        case 32: e = launch_bwd<32, 1, false>(gp, lds, stream); break;
+        case 64: e = launch_bwd<64, 1, false>(gp, lds, stream); break;
+        default: return hipErrorInvalidValue;
+    }
+    if (e != hipSuccess) return e;
+    const int64_t n = (int64_t)gp.p.K * gp.p.n_samples;
+    if (n == 0) return hipSuccess;
+    hipLaunchKernelGGL(samples_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, gp,
+                       grad_samples);
+    return hipGetLastError();
+}
+
+}  // namespace pm

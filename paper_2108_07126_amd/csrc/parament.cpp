@@ -19,6 +19,7 @@ namespace pm {
 hipError_t launch_mfma(int D, bool fp64, const PropParams& p, hipStream_t stream);
 hipError_t launch_valu(int D, bool fp64, const PropParams& p, hipStream_t stream);
 int mfma_chains_per_block(int D);
+hipError_t launch_backward(int D, const GradParams& gp, double* grad_samples, hipStream_t stream);
 }  // namespace pm
 
 using cplx = std::complex<double>;
@@ -54,6 +55,19 @@ struct pm_ctx {
     size_t u_bytes = 0;
     void* d_slices = nullptr;
     size_t slices_bytes = 0;
+    // gradient: FP64 MFMA engine (d <= 4 embedded in 16) and its workspace
+    pm::EngineInfo geng{};
+    double* d_basis_grad = nullptr;   // null: d_basis already has the gradient engine's layout
+    double* d_chain = nullptr;
+    size_t chain_bytes = 0;
+    double* d_gw = nullptr;
+    size_t gw_bytes = 0;
+    double* d_UT = nullptr;
+    size_t ut_bytes = 0;
+    double* d_W = nullptr;
+    size_t w_bytes = 0;
+    double* d_grad = nullptr;
+    size_t grad_bytes = 0;
     std::string err;
 };
 
@@ -307,9 +321,9 @@ int64_t auto_chunk(const pm::EngineInfo& e, int64_t N) {
     return ((c + u - 1) / u) * u;
 }
 
-pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt, double* d_U,
-                 void* d_slices, hipStream_t stream) {
-    const pm::EngineInfo& e = ctx->eng;
+// Workspace and kernel parameters of one propagation on engine e.
+pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, const double* basis, const double* d_samples,
+                  int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out) {
     const int64_t N = n_slices_of(ctx->order, n_samples);
     int64_t chunk = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N);
     chunk = ((chunk + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
@@ -323,9 +337,9 @@ pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double
                 sizeof(unsigned) * (size_t)(2 * leaves + 64), "tree tickets", true);
     if (st != PM_OK) return st;
 
-    pm::PropParams p;
+    pm::PropParams& p = *out;
     std::memset(&p, 0, sizeof(p));
-    p.basis = ctx->d_basis;
+    p.basis = basis;
     p.samples = d_samples;
     p.n_samples = n_samples;
     p.n_slices = N;
@@ -353,8 +367,52 @@ pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double
                    (size_t)ctx->M * e.D * e.D * 16 <= 64 * 1024) ? 1 : 0;
     std::memcpy(p.pair_a, ctx->pair_a, sizeof(p.pair_a));
     std::memcpy(p.pair_b, ctx->pair_b, sizeof(p.pair_b));
-    hipError_t he = pm::launch_propagate(e, ctx->precision, p, stream);
+    return PM_OK;
+}
+
+pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt, double* d_U,
+                 void* d_slices, hipStream_t stream) {
+    pm::PropParams p;
+    pm_status st = prepare(ctx, ctx->eng, ctx->d_basis, d_samples, n_samples, dt, d_U, d_slices, &p);
+    if (st != PM_OK) return st;
+    hipError_t he = pm::launch_propagate(ctx->eng, ctx->precision, p, stream);
     if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
+    return PM_OK;
+}
+
+// Gradient: forward on the FP64 MFMA engine keeping chain products and every
+// tree node (U(T) into ctx->d_UT), then the backward kernels.
+pm_status launch_grad(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt,
+                      const double* d_W, double* d_grad, hipStream_t stream, bool run_forward,
+                      bool run_backward) {
+    const pm::EngineInfo& e = ctx->geng;
+    const double* basis = ctx->d_basis_grad ? ctx->d_basis_grad : ctx->d_basis;
+    pm::PropParams p;
+    pm_status st = ensure(ctx, (void**)&ctx->d_UT, &ctx->ut_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "U(T)");
+    if (st != PM_OK) return st;
+    st = prepare(ctx, e, basis, d_samples, n_samples, dt, ctx->d_UT, nullptr, &p);
+    if (st != PM_OK) return st;
+    st = ensure(ctx, (void**)&ctx->d_chain, &ctx->chain_bytes, (size_t)p.n_chains * e.D * e.D * 16,
+                "chain products");
+    if (st != PM_OK) return st;
+    p.chain_out = ctx->d_chain;
+    p.store_nodes = 1;
+    hipError_t he;
+    if (run_forward) {
+        he = pm::launch_propagate(e, PM_FP64, p, stream);
+        if (he != hipSuccess) return hip_fail(ctx, he, "forward launch");
+    }
+    if (!run_backward) return PM_OK;
+    st = ensure(ctx, (void**)&ctx->d_gw, &ctx->gw_bytes, sizeof(double) * (size_t)p.n_slices * p.M,
+                "weight gradients");
+    if (st != PM_OK) return st;
+    pm::GradParams gp;
+    gp.p = p;
+    gp.W = d_W;
+    gp.UT = ctx->d_UT;
+    gp.gw = ctx->d_gw;
+    he = pm::launch_backward(e.D, gp, d_grad, stream);
+    if (he != hipSuccess) return hip_fail(ctx, he, "backward launch");
     return PM_OK;
 }
 
@@ -539,6 +597,12 @@ pm_status pm_destroy(pm_ctx* ctx) {
         dfree(ctx->d_counters);
         dfree(ctx->d_samples);
         dfree(ctx->d_U);
+        dfree(ctx->d_basis_grad);
+        dfree(ctx->d_chain);
+        dfree(ctx->d_gw);
+        dfree(ctx->d_UT);
+        dfree(ctx->d_W);
+        dfree(ctx->d_grad);
         if (ctx->d_slices) (void)hipFree(ctx->d_slices);
         ctx->d_slices = nullptr;
     }
@@ -603,6 +667,27 @@ pm_status pm_set_hamiltonian(pm_ctx* ctx, int64_t dim, const double* H0, int64_t
     }
     he = hipMemcpy(ctx->d_basis, lay.data(), lay.size() * sizeof(double), hipMemcpyHostToDevice);
     if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy basis");
+    // the gradient runs on the FP64 MFMA engine; d <= 4 gets its own
+    // embedded basis there
+    dfree(ctx->d_basis_grad);
+    if (ctx->precision == PM_FP64) {
+        pm::EngineInfo ge;
+        pm::pick_engine(dim <= 16 ? 16 : (int)dim, PM_FP64, &ge);
+        ctx->geng = ge;
+        if (e.kind != pm::ENGINE_MFMA) {
+            std::vector<double> glay((size_t)pm::basis_layout_doubles(ge, M));
+            pm::basis_to_layout(ge, M, (int)dim, flat.data(), glay.data());
+            he = hipMalloc((void**)&ctx->d_basis_grad, glay.size() * sizeof(double));
+            if (he != hipSuccess) {
+                ctx->d_basis_grad = nullptr;
+                (void)hipGetLastError();
+                ctx->ready = false;
+                return fail(ctx, PM_E_OOM, "hipMalloc failed for the gradient basis");
+            }
+            he = hipMemcpy(ctx->d_basis_grad, glay.data(), glay.size() * sizeof(double), hipMemcpyHostToDevice);
+            if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy gradient basis");
+        }
+    }
     ctx->dim = dim;
     ctx->n_ctrl = n_ctrl;
     ctx->order = order;
@@ -672,6 +757,93 @@ pm_status pm_equiprop(pm_ctx* ctx, const double* samples, int64_t n_samples, dou
         he = hipMemcpy(slices_out, ctx->d_slices, slbytes, hipMemcpyDeviceToHost);
         if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy slices");
     }
+    return PM_OK;
+}
+
+pm_status check_grad_args(pm_ctx* ctx) {
+    if (ctx->precision != PM_FP64)
+        return fail(ctx, PM_E_UNSUPPORTED, "gradients are computed by PM_FP64 contexts");
+    return PM_OK;
+}
+
+pm_status pm_backward_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samples, double dt,
+                          const double* W_dev, double* grad_dev, double* U_out_dev, void* stream) {
+    pm_status s = check_prop_args(ctx, n_samples, dt);
+    if (s != PM_OK) return s;
+    s = check_grad_args(ctx);
+    if (s != PM_OK) return s;
+    if (!W_dev || (ctx->n_ctrl > 0 && (!samples_dev || !grad_dev)))
+        return fail(ctx, PM_E_INVALID_ARG, "null pointer");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    s = launch_grad(ctx, samples_dev, n_samples, dt, W_dev, grad_dev, st, true, true);
+    if (s != PM_OK) return s;
+    if (U_out_dev) {
+        hipError_t he = hipMemcpyAsync(U_out_dev, ctx->d_UT, 16 * ctx->dim * ctx->dim,
+                                       hipMemcpyDeviceToDevice, st);
+        if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpyAsync U");
+    }
+    return PM_OK;
+}
+
+pm_status pm_fidelity_grad(pm_ctx* ctx, const double* samples, int64_t n_samples, double dt,
+                           const double* V, double* loss, double* grad, double* U_out) {
+    pm_status s = check_prop_args(ctx, n_samples, dt);
+    if (s != PM_OK) return s;
+    s = check_grad_args(ctx);
+    if (s != PM_OK) return s;
+    if (!V || !loss || (ctx->n_ctrl > 0 && (!samples || !grad)))
+        return fail(ctx, PM_E_INVALID_ARG, "null pointer");
+    const int64_t K = ctx->n_ctrl, d = ctx->dim;
+    for (int64_t i = 0; i < K * n_samples; ++i)
+        if (!std::isfinite(samples[i])) return fail(ctx, PM_E_INVALID_ARG, "non-finite control sample");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    s = ensure(ctx, (void**)&ctx->d_samples, &ctx->samples_bytes,
+               sizeof(double) * (size_t)std::max<int64_t>(K * n_samples, 1), "samples");
+    if (s != PM_OK) return s;
+    s = ensure(ctx, (void**)&ctx->d_W, &ctx->w_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "W");
+    if (s != PM_OK) return s;
+    s = ensure(ctx, (void**)&ctx->d_grad, &ctx->grad_bytes,
+               sizeof(double) * (size_t)std::max<int64_t>(K * n_samples, 1), "gradient");
+    if (s != PM_OK) return s;
+    hipError_t he;
+    if (K > 0) {
+        he = hipMemcpy(ctx->d_samples, samples, sizeof(double) * K * n_samples, hipMemcpyHostToDevice);
+        if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy samples");
+    }
+    s = launch_grad(ctx, ctx->d_samples, n_samples, dt, nullptr, nullptr, nullptr, true, false);
+    if (s != PM_OK) return s;
+    std::vector<double> U(2 * d * d), W(2 * d * d);
+    he = hipMemcpy(U.data(), ctx->d_UT, 16 * d * d, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy U");
+    // L = 1 - |g|^2 / d^2, g = Tr(V^H U);  W = 2 dL/d conj(U) = -(2 g / d^2) V
+    cplx gg(0, 0);
+    for (int64_t a = 0; a < d; ++a)
+        for (int64_t b = 0; b < d; ++b)
+            gg += std::conj(cplx(V[(a * d + b) * 2], V[(a * d + b) * 2 + 1])) *
+                  cplx(U[(a * d + b) * 2], U[(a * d + b) * 2 + 1]);
+    const double d2 = (double)(d * d);
+    const cplx f = -2.0 * gg / d2;
+    for (int64_t i = 0; i < d * d; ++i) {
+        const cplx w = f * cplx(V[2 * i], V[2 * i + 1]);
+        W[2 * i] = w.real();
+        W[2 * i + 1] = w.imag();
+    }
+    he = hipMemcpy(ctx->d_W, W.data(), 16 * d * d, hipMemcpyHostToDevice);
+    if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy W");
+    // the backward reuses the forward's checkpoints (same launch parameters)
+    s = launch_grad(ctx, ctx->d_samples, n_samples, dt, ctx->d_W, ctx->d_grad, nullptr, false, true);
+    if (s != PM_OK) return s;
+    he = hipDeviceSynchronize();
+    if (he != hipSuccess) return hip_fail(ctx, he, "gradient kernels");
+    if (K > 0) {
+        he = hipMemcpy(grad, ctx->d_grad, sizeof(double) * K * n_samples, hipMemcpyDeviceToHost);
+        if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy gradient");
+    }
+    *loss = 1.0 - std::norm(gg) / d2;
+    if (U_out) std::memcpy(U_out, U.data(), 16 * d * d);
     return PM_OK;
 }
 

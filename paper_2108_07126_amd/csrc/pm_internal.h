@@ -27,6 +27,8 @@ struct PropParams {
     double* nodes;            // tree nodes, [2 * n_leaves][D][D] complex128
     unsigned* counters;       // [2 * n_leaves] pair tickets, zero between launches
     double* U_out;            // [du][du] complex128
+    double* chain_out;        // nullptr or [n_chains][D][D] complex128 chain products
+    int store_nodes;          // keep every tree node (gradient checkpoints)
     double h;
     double theta[kMaxDeg + 1];   // Taylor thresholds for the working precision
     int K, M, order, du;
@@ -34,6 +36,14 @@ struct PropParams {
     int basis_lds;               // MFMA engine: block keeps a copy of the basis in LDS
     uint8_t pair_a[kMaxBasis];   // order 4: control indices of i[H_a, H_b]
     uint8_t pair_b[kMaxBasis];
+};
+
+// The gradient kernels' arguments.
+struct GradParams {
+    PropParams p;       // forward parameters; p.nodes and p.chain_out filled by the forward
+    const double* W;    // [du][du] complex128, dL = Re Tr(W^H dU(T))
+    const double* UT;   // [du][du] complex128, U(T) of that forward
+    double* gw;         // [N][M] dL / d w_{j,m}
 };
 
 // Engines.  D is the (padded) engine dimension.
