@@ -89,7 +89,7 @@ constexpr int min_waves_per_eu() {
     return D == 64 ? 4 : (std::is_same<T, double>::value ? 3 : 4);
 }
 
-template <typename T, int D, int NT, bool BL>
+template <typename T, int D, int NT, bool BL, int PMODE>
 __global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
 __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, D>(), 8)))
 propagate_mfma(PropParams p) {
@@ -159,7 +159,7 @@ propagate_mfma(PropParams p) {
             Gt.im[r] = (T)ldexp(gim[r], -s);
         }
         // exponentiate
-        Tile<T> U = taylor_exp<G, T>(Gt, m, L, s0, s1);
+        Tile<T> U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
         if (s > 0) {
             if constexpr (std::is_same<T, double>::value) {
                 U = square_n<G, double>(U, s, L, s0);
@@ -173,7 +173,7 @@ propagate_mfma(PropParams p) {
         slot_store<G, T>(s0, U, L);
         slot_store<G, T>(s1, Q, L);
         team_sync<G>();
-        Q = slot_mul<G, T>(s0, s1, L);
+        Q = mulT<G, T, PMODE>(s0, s1, L);
     }
     Tile<double> Qd = relayout<G, double>(Q, s0, L);
     if (p.chain_out && chain < p.n_chains)
@@ -201,25 +201,28 @@ constexpr size_t lds_fixed_bytes() {
     return sizeof(double) * ((size_t)NT * 2 * G::SLOT + (size_t)G::TD * D + 2);
 }
 
-template <typename T, int D, int NT, bool BL>
+template <typename T, int D, int NT, bool BL, int PMODE>
 hipError_t launch_one(const PropParams& p, hipStream_t stream) {
     using G = Geo<D, NT>;
     const size_t lds = lds_fixed_bytes<D, NT>() + (BL ? sizeof(double) * (size_t)p.M * G::TW * 512 : 0);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)propagate_mfma<T, D, NT, BL>,
+        hipError_t e = hipFuncSetAttribute((const void*)propagate_mfma<T, D, NT, BL, PMODE>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((propagate_mfma<T, D, NT, BL>), dim3((unsigned)p.n_leaves), dim3(G::THREADS), lds,
+    hipLaunchKernelGGL((propagate_mfma<T, D, NT, BL, PMODE>), dim3((unsigned)p.n_leaves), dim3(G::THREADS), lds,
                        stream, p);
     return hipGetLastError();
 }
 
-template <typename T, int D, int NT>
+template <typename T, int D, int NT, int PMODE>
 hipError_t launch_bl(const PropParams& p, hipStream_t stream) {
-    return p.basis_lds ? launch_one<T, D, NT, true>(p, stream) : launch_one<T, D, NT, false>(p, stream);
+    if constexpr (D == 16) {
+        if (p.basis_lds) return launch_one<T, D, NT, true, PMODE>(p, stream);
+    }
+    return launch_one<T, D, NT, false, PMODE>(p, stream);
 }
 
 }  // namespace
@@ -227,11 +230,22 @@ hipError_t launch_bl(const PropParams& p, hipStream_t stream) {
 // Teams per block for the one-wave teams of D = 16.
 constexpr int kNT16 = 4;
 
-hipError_t launch_mfma(int D, bool fp64, const PropParams& p, hipStream_t stream) {
+template <typename T, int PMODE>
+hipError_t launch_dims(int D, const PropParams& p, hipStream_t stream) {
     switch (D) {
-        case 16: return fp64 ? launch_bl<double, 16, kNT16>(p, stream) : launch_bl<float, 16, kNT16>(p, stream);
-        case 32: return fp64 ? launch_bl<double, 32, 1>(p, stream) : launch_bl<float, 32, 1>(p, stream);
-        case 64: return fp64 ? launch_bl<double, 64, 1>(p, stream) : launch_bl<float, 64, 1>(p, stream);
+        case 16: return launch_bl<T, 16, kNT16, PMODE>(p, stream);
+        case 32: return launch_bl<T, 32, 1, PMODE>(p, stream);
+        case 64: return launch_bl<T, 64, 1, PMODE>(p, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
+
+hipError_t launch_mfma(int D, int precision, const PropParams& p, hipStream_t stream) {
+    switch (precision) {
+        case PM_FP64: return launch_dims<double, 0>(D, p, stream);
+        case PM_FP32: return launch_dims<float, 0>(D, p, stream);
+        case PM_FP32_3M: return launch_dims<float, 1>(D, p, stream);
+        case PM_BF16_SPLIT: return launch_dims<float, 2>(D, p, stream);
         default: return hipErrorInvalidValue;
     }
 }

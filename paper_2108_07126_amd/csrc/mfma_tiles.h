@@ -156,6 +156,117 @@ __device__ __forceinline__ Tile<T> slot_mul(const double* A, const double* B, co
     return out;
 }
 
+// Complex product as three real products (3M): T1 = Ar Br, T2 = Ai Bi,
+// T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2.  FP32 MFMA.
+template <class G>
+__device__ __forceinline__ Tile<float> slot_mul_3m(const double* A, const double* B, const Lane& L) {
+    const float* Are = reinterpret_cast<const float*>(A);
+    const float* Aim = Are + G::PLANE;
+    const float* Bre = reinterpret_cast<const float*>(B);
+    const float* Bim = Bre + G::PLANE;
+    f4_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+    const int arow = (16 * L.TI + L.j) * G::LD;
+    const int bcol = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int kb = 0; kb < G::D / 4; ++kb) {
+        const int k = 4 * kb + L.g;
+        const float ar = Are[arow + k], ai = Aim[arow + k];
+        const float br = Bre[k * G::LD + bcol], bi = Bim[k * G::LD + bcol];
+        t1 = mfma16(ar, br, t1);
+        t2 = mfma16(ai, bi, t2);
+        t3 = mfma16(ar + ai, br + bi, t3);
+    }
+    Tile<float> out;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out.re[r] = t1[r] - t2[r];
+        out.im[r] = t3[r] - t1[r] - t2[r];
+    }
+    return out;
+}
+
+typedef short s4_t __attribute__((ext_vector_type(4)));
+
+// x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even).
+__device__ __forceinline__ void split_bf16x4(const float* x, s4_t& hi, s4_t& lo) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        const __bf16 h = (__bf16)x[q];
+        const __bf16 l = (__bf16)(x[q] - (float)h);
+        hi[q] = (short)__builtin_bit_cast(unsigned short, h);
+        lo[q] = (short)__builtin_bit_cast(unsigned short, l);
+    }
+}
+
+__device__ __forceinline__ f4_t mfma_bf16(s4_t a, s4_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+}
+
+// 3M complex product on BF16 hi/lo split operands with FP32 accumulation:
+// each real product a b is taken as a_hi b_hi + a_hi b_lo + a_lo b_hi (the
+// a_lo b_lo term is below FP32 rounding of the result's scale).  The 16x16x16
+// BF16 MFMA takes four consecutive k per lane group: A[i][16 kb + 4 g + q],
+// B[16 kb + 4 g + q][j].
+template <class G>
+__device__ __forceinline__ Tile<float> slot_mul_bf16s(const double* A, const double* B, const Lane& L) {
+    const float* Are = reinterpret_cast<const float*>(A);
+    const float* Aim = Are + G::PLANE;
+    const float* Bre = reinterpret_cast<const float*>(B);
+    const float* Bim = Bre + G::PLANE;
+    f4_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+    const int arow = (16 * L.TI + L.j) * G::LD;
+    const int bcol = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int kb = 0; kb < G::D / 16; ++kb) {
+        float ar[4], ai[4], as[4], br[4], bi[4], bs[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+            const int k = 16 * kb + 4 * L.g + q;
+            ar[q] = Are[arow + k];
+            ai[q] = Aim[arow + k];
+            br[q] = Bre[k * G::LD + bcol];
+            bi[q] = Bim[k * G::LD + bcol];
+            as[q] = ar[q] + ai[q];
+            bs[q] = br[q] + bi[q];
+        }
+        s4_t arh, arl, aih, ail, ash, asl, brh, brl, bih, bil, bsh, bsl;
+        split_bf16x4(ar, arh, arl);
+        split_bf16x4(ai, aih, ail);
+        split_bf16x4(as, ash, asl);
+        split_bf16x4(br, brh, brl);
+        split_bf16x4(bi, bih, bil);
+        split_bf16x4(bs, bsh, bsl);
+        t1 = mfma_bf16(arh, brh, t1);
+        t2 = mfma_bf16(aih, bih, t2);
+        t3 = mfma_bf16(ash, bsh, t3);
+        t1 = mfma_bf16(arh, brl, t1);
+        t2 = mfma_bf16(aih, bil, t2);
+        t3 = mfma_bf16(ash, bsl, t3);
+        t1 = mfma_bf16(arl, brh, t1);
+        t2 = mfma_bf16(ail, bih, t2);
+        t3 = mfma_bf16(asl, bsh, t3);
+    }
+    Tile<float> out;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out.re[r] = t1[r] - t2[r];
+        out.im[r] = t3[r] - t1[r] - t2[r];
+    }
+    return out;
+}
+
+// Product modes of the FP32 kernels: 0 four real products, 1 3M, 2 BF16-split 3M.
+template <class G, typename T, int PMODE>
+__device__ __forceinline__ Tile<T> mulT(const double* A, const double* B, const Lane& L) {
+    if constexpr (std::is_same<T, double>::value || PMODE == 0) {
+        return slot_mul<G, T>(A, B, L);
+    } else if constexpr (PMODE == 1) {
+        return slot_mul_3m<G>(A, B, L);
+    } else {
+        return slot_mul_bf16s<G>(A, B, L);
+    }
+}
+
 // ||G||_1 of the Hermitian G, taken as its max row sum (equal for Hermitian
 // matrices), FP64 sums of entry bounds; same value in every lane.  A row of a
 // tile lives in the 16 lanes of one lane group (one register), so row sums
@@ -189,7 +300,7 @@ __device__ __forceinline__ double team_norm1(const double* gre, const double* gi
 
 // exp(-i G) for a (pre-scaled) Hermitian tile set by the degree-m Taylor
 // polynomial, split as C(Y) - i G S'(Y).  Uses slots s0, s1.
-template <class G, typename T>
+template <class G, typename T, int PMODE = 0>
 __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s0, double* s1) {
     Tile<T> C = ident<T>(L);
     Tile<T> S;
@@ -201,7 +312,7 @@ __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s
         team_sync<G>();
         slot_store<G, T>(s0, Gt, L);
         team_sync<G>();
-        Tile<T> P = slot_mul<G, T>(s0, s0, L);   // Y = G G
+        Tile<T> P = mulT<G, T, PMODE>(s0, s0, L);   // Y = G G
         Tile<T> Sp = ident<T>(L);
         axpy(C, cos_coef(1), P);
         if (qs >= 1) axpy(Sp, sin_coef(1), P);
@@ -211,12 +322,12 @@ __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s
             team_sync<G>();
             for (int k = 2; k <= qc; ++k) {
                 if (k == 2) {
-                    P = slot_mul<G, T>(s1, s1, L);
+                    P = mulT<G, T, PMODE>(s1, s1, L);
                 } else {
                     team_sync<G>();
                     slot_store<G, T>(s0, P, L);
                     team_sync<G>();
-                    P = slot_mul<G, T>(s0, s1, L);
+                    P = mulT<G, T, PMODE>(s0, s1, L);
                 }
                 axpy(C, cos_coef(k), P);
                 if (k <= qs) axpy(Sp, sin_coef(k), P);
@@ -227,7 +338,7 @@ __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s
             slot_store<G, T>(s0, Gt, L);
             slot_store<G, T>(s1, Sp, L);
             team_sync<G>();
-            S = slot_mul<G, T>(s0, s1, L);
+            S = mulT<G, T, PMODE>(s0, s1, L);
         } else {
             S = Gt;
         }

@@ -16,7 +16,7 @@
 #include "pm_internal.h"
 
 namespace pm {
-hipError_t launch_mfma(int D, bool fp64, const PropParams& p, hipStream_t stream);
+hipError_t launch_mfma(int D, int precision, const PropParams& p, hipStream_t stream);
 hipError_t launch_valu(int D, bool fp64, const PropParams& p, hipStream_t stream);
 int mfma_chains_per_block(int D);
 hipError_t launch_backward(int D, const GradParams& gp, double* grad_samples, hipStream_t stream);
@@ -422,7 +422,7 @@ namespace pm {
 
 bool pick_engine(int du, int precision, EngineInfo* out) {
     if (du < 1 || du > PM_MAX_DIM) return false;
-    if (precision != PM_FP64 && precision != PM_FP32) return false;
+    if (unit_roundoff(precision) < 0) return false;
     EngineInfo e{};
     if (du <= 4) {
         e.kind = ENGINE_VALU;
@@ -471,9 +471,8 @@ void basis_to_layout(const EngineInfo& e, int M, int du, const double* basis, do
 
 hipError_t launch_propagate(const EngineInfo& e, int precision, const PropParams& p,
                             hipStream_t stream) {
-    const bool fp64 = precision == PM_FP64;
-    if (e.kind == ENGINE_VALU) return launch_valu(e.D, fp64, p, stream);
-    return launch_mfma(e.D, fp64, p, stream);
+    if (e.kind == ENGINE_VALU) return launch_valu(e.D, precision == PM_FP64, p, stream);
+    return launch_mfma(e.D, precision, p, stream);
 }
 
 }  // namespace pm
