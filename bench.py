@@ -112,6 +112,7 @@ def main():
     ap.add_argument("--warmup", type=int, default=5)
     ap.add_argument("--skip-cpu", action="store_true", help="leave out the oracle CPU baseline")
     ap.add_argument("--skip-fixed-error", action="store_true")
+    ap.add_argument("--skip-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU only: this build has no multi-GPU path "
@@ -135,28 +136,30 @@ def main():
         ctx.set_hamiltonian(w.H0, w.Hk, w.order)
         return ctx
 
-    ctx64 = make(pm.PM_FP64)
-    U64 = torch.zeros((d, d), dtype=torch.complex128, device=dev)
-    wall64, k64 = time_launches(lambda: ctx64.equiprop_dev(s_dev, w.h, U64), args.steps, args.warmup)
-    Ug64 = U64.cpu().numpy()
+    modes = [("fp64", pm.PM_FP64), ("fp32", pm.PM_FP32), ("fp32_3m", pm.PM_FP32_3M),
+             ("bf16_split", pm.PM_BF16_SPLIT)]
+    ctxs, timing, Ug = {}, {}, {}
+    for name, prec in modes:
+        ctx = make(prec)
+        U = torch.zeros((d, d), dtype=torch.complex128, device=dev)
+        steps = args.steps if name == "fp64" else max(5, args.steps // 2)
+        timing[name] = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U), steps, args.warmup)
+        Ug[name] = U.cpu().numpy()
+        ctxs[name] = ctx
+    wall64, k64 = timing["fp64"]
 
-    ctx32 = make(pm.PM_FP32)
-    U32 = torch.zeros((d, d), dtype=torch.complex128, device=dev)
-    wall32, k32 = time_launches(lambda: ctx32.equiprop_dev(s_dev, w.h, U32), args.steps, args.warmup)
-    Ug32 = U32.cpu().numpy()
-
-    # per-slice output variant (a4): 512 MiB of complex128 propagators per step
+    # per-slice output variant: 512 MiB of complex128 propagators per step
     sl = torch.empty((N, d, d), dtype=torch.complex128, device=dev)
-    wall64s, k64s = time_launches(lambda: ctx64.equiprop_dev(s_dev, w.h, U64, sl), max(5, args.steps // 2), 2)
+    U64 = torch.zeros((d, d), dtype=torch.complex128, device=dev)
+    wall64s, k64s = time_launches(lambda: ctxs["fp64"].equiprop_dev(s_dev, w.h, U64, sl),
+                                  max(5, args.steps // 2), 2)
     del sl
 
     # leaves used by the automatic chunking (same rule as the library)
-    resident = 256 * 8
-    chunk = max(1, math.ceil(N / (2 * resident)))
+    chunk = max(1, math.ceil(N / (256 * 8)))
     leaves = math.ceil(N / chunk)
-    flops64 = algorithmic_flops(pm, w, 0, leaves)
-    flops32 = algorithmic_flops(pm, w, 1, leaves)
-    ach64 = flops64 / (k64 * 1e-3) / 1e12
+    flops = {name: algorithmic_flops(pm, w, 0 if name == "fp64" else 1, leaves) for name, _ in modes}
+    ach64 = flops["fp64"] / (k64 * 1e-3) / 1e12
 
     out = {
         "metric": METRIC,
@@ -175,15 +178,45 @@ def main():
                    "n_slices": N, "order": 4, "dt": w.h, "output": "U(T)", "chunk": chunk, "leaves": leaves},
         "roofline": {"bound": "mfma", "achieved": ach64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach64 / PEAK_FP64_TFLOPS, "traffic": None,
-                     "kernel": "propagate_mfma<double,16,4>", "kernel_ms": k64,
-                     "algorithmic_flop_per_launch": flops64},
-        "fp32": {"steps_per_s": N / (wall32 * 1e-3), "ms_per_step": wall32, "kernel_ms": k32,
-                 "achieved_tflops": flops32 / (k32 * 1e-3) / 1e12, "peak_tflops": PEAK_FP32_TFLOPS},
+                     "kernel": "propagate_mfma<double,16,4,true,0>", "kernel_ms": k64,
+                     "algorithmic_flop_per_launch": flops["fp64"]},
+        "precisions": {name: {"steps_per_s": N / (timing[name][0] * 1e-3), "ms_per_step": timing[name][0],
+                              "kernel_ms": timing[name][1],
+                              "achieved_tflops": flops[name] / (timing[name][1] * 1e-3) / 1e12}
+                       for name, _ in modes},
         "fp64_with_slices": {"steps_per_s": N / (wall64s * 1e-3), "kernel_ms": k64s,
                              "slice_bytes": N * d * d * 16,
                              "hbm_write_gbs": N * d * d * 16 / (k64s * 1e-3) / 1e9},
-        "grad": None,
     }
+
+    # adjoint gradient: fidelity-grad evals/s on the 3-qubit register workload
+    wg = synth.qubit_register()
+    cg = pm.Context(0, pm.PM_FP64)
+    cg.set_hamiltonian(wg.H0, wg.Hk, 2)
+    sg = torch.from_numpy(wg.samples).to(dev)
+    Wt = torch.zeros((8, 8), dtype=torch.complex128, device=dev)
+    gt = torch.zeros_like(sg)
+    Ut = torch.zeros((8, 8), dtype=torch.complex128, device=dev)
+    loss, grad_h, Uh = cg.fidelity_grad(wg.samples, wg.h, wg.target)   # host entry point (also warms up)
+    g_tr = np.trace(wg.target.conj().T @ Uh)
+    Wt.copy_(torch.from_numpy(-(2 * g_tr / 64) * wg.target))
+    wall_g, k_g = time_launches(lambda: cg.backward_dev(sg, wg.h, Wt, gt, Ut), max(5, args.steps), 2)
+    out["grad"] = {"workload": "qubit_register_d8_K4_N4096", "evals_per_s": 1e3 / wall_g, "ms_per_eval": wall_g,
+                   "gpu_ms_per_eval": k_g, "params": int(wg.samples.size), "loss": loss}
+
+    # batched uneven instances: one persistent, graph-captured launch
+    if not args.skip_batch:
+        ws = synth.batched_instances()
+        nsl = int(sum(x.n_slices for x in ws))
+        bt = pm.Batch(0, pm.PM_FP32_3M)
+        t0 = time.perf_counter()
+        bt.set(ws)
+        t_set = time.perf_counter() - t0
+        wall_b, k_b = time_launches(lambda: bt.run(torch.cuda.current_stream()), 3, 1)
+        out["batch"] = {"workload": "512 uneven instances (d 2..64, K 1..4, N 1e3..1e5, orders 2/4)",
+                        "precision": "fp32_3m", "slices": nsl, "packets": bt.n_packets, "ms_per_run": wall_b,
+                        "steps_per_s": nsl / (wall_b * 1e-3), "set_s": t_set}
+        bt.close()
 
     Uo = None
     if not args.skip_cpu:
@@ -193,32 +226,33 @@ def main():
         dt_cpu = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": N / dt_cpu, "unit": "steps/s", "cores": blas_threads(), "kind": "oracle",
                                "sample": f"the whole workload ({N} slices, one run, {dt_cpu:.1f} s)"}
-        out["error_vs_oracle"] = {"fp64": orc.relative_frobenius(Ug64, Uo), "fp32": orc.relative_frobenius(Ug32, Uo)}
+        out["error_vs_oracle"] = {name: orc.relative_frobenius(Ug[name], Uo) for name, _ in modes}
+        _, go = orc.control_gradient(wg.H0, wg.Hk, wg.samples, wg.h, 2,
+                                     orc.fidelity_grad_U(orc.propagate(wg.H0, wg.Hk, wg.samples, wg.h, 2), wg.target))
+        out["grad"]["rel_err_vs_oracle"] = float(np.max(np.abs(grad_h - go)) / np.max(np.abs(go)))
 
     if not args.skip_fixed_error and Uo is not None:
         import oracle.propagator as orc
         # same T, coarser slicing: smallest N=2^n meeting each target error
         T = N * w.h
-        res = {}
-        for name, ctx in (("fp64", ctx64), ("fp32", ctx32)):
+        res = {"reference": "oracle at the workload's own N (2^17 slices)"}
+        summ = {}
+        for name, _ in modes:
             errs = {}
             for n in range(8, 18):
                 nn = 2 ** n
                 wn = synth.random_qudit(n_slices=nn, h=T / nn)
                 sd = torch.from_numpy(wn.samples).to(dev)
                 Ud = torch.zeros((d, d), dtype=torch.complex128, device=dev)
-                wall, _ = time_launches(lambda: ctx.equiprop_dev(sd, wn.h, Ud), 5, 2)
+                wall, _ = time_launches(lambda: ctxs[name].equiprop_dev(sd, wn.h, Ud), 5, 2)
                 errs[nn] = (orc.relative_frobenius(Ud.cpu().numpy(), Uo), wall)
             res[name] = {str(k): {"err": v[0], "ms": v[1]} for k, v in errs.items()}
             for eps in (1e-4, 1e-6):
                 ok = [k for k, v in errs.items() if v[0] <= eps]
-                key = f"eps_{eps:.0e}"
-                if ok:
-                    k = min(ok)
-                    res.setdefault("summary", {})[f"{name}_{key}"] = {
-                        "n_slices": k, "ms": errs[k][1], "steps_per_s": k / (errs[k][1] * 1e-3)}
-                else:
-                    res.setdefault("summary", {})[f"{name}_{key}"] = None
+                summ[f"{name}_eps_{eps:.0e}"] = ({"n_slices": min(ok), "ms": errs[min(ok)][1],
+                                                  "steps_per_s": min(ok) / (errs[min(ok)][1] * 1e-3)}
+                                                 if ok else None)
+        res["summary"] = summ
         out["fixed_error"] = res
 
     print(json.dumps(out), flush=True)

@@ -140,6 +140,58 @@ pm_status pm_fidelity_grad(pm_ctx *ctx, const double *samples, int64_t n_samples
                            double dt, const double *V, double *loss, double *grad,
                            double *U_out);
 
+/* ---- batches of independent, uneven instances ---------------------------
+ * Many propagation problems (any mix of dimensions, control counts, slice
+ * counts and orders) in one persistent launch on one device.  Each instance
+ * follows the same conventions as a single context; its U(T) lands in a
+ * concatenated output [instance][dim][dim] complex128.  Chains of
+ * consecutive slices from every instance are grouped in packets (a block's
+ * worth of work) and served longest-first from a shared queue; the launch is
+ * captured once in a HIP graph and replayed.  Instances of dimension <= 16
+ * are embedded in 16 (32 and 64 use their own tile layouts). */
+typedef struct pm_batch pm_batch;
+
+typedef struct pm_instance {
+    int64_t dim;             /* 1..PM_MAX_DIM                                  */
+    int64_t n_ctrl;          /* 0..8                                           */
+    int order;               /* 2 or 4                                         */
+    const double *H0;        /* host complex128 [dim][dim]                     */
+    const double *Hk;        /* host complex128 [n_ctrl][dim][dim] (or NULL)   */
+    const double *samples;   /* host float64 [n_ctrl][n_samples] (or NULL)     */
+    int64_t n_samples;       /* order 2: N; order 4: 2N + 1                    */
+    double dt;               /* slice width h                                  */
+} pm_instance;
+
+/* Create / release a batch on `device` computing in `precision`. */
+pm_status pm_batch_create(pm_batch **out, int device, int precision);
+pm_status pm_batch_destroy(pm_batch *b);
+
+/* Validate, build every instance's basis and plan, and upload everything
+ * (copies the caller's buffers; replaces a previous set).  Inputs are checked
+ * like pm_set_hamiltonian / pm_equiprop; on error nothing is kept. */
+pm_status pm_batch_set(pm_batch *b, const pm_instance *inst, int64_t n_inst);
+
+/* Slices per chain for the instances of embedding dimension dim_class (16, 32
+ * or 64); 0 restores the default.  Takes effect at the next pm_batch_set. */
+pm_status pm_batch_set_chunk(pm_batch *b, int dim_class, int64_t chunk);
+
+/* Enqueue the whole batch on `stream` (a hipStream_t, NULL = null stream). */
+pm_status pm_batch_run(pm_batch *b, void *stream);
+
+/* Synchronise and copy every U(T) (concatenated complex128, instance order)
+ * into the host buffer U_out of n_doubles doubles (2 * sum dim^2 needed). */
+pm_status pm_batch_result(pm_batch *b, double *U_out, int64_t n_doubles);
+
+/* Device pointer to the concatenated results (valid until the next
+ * pm_batch_set or pm_batch_destroy). */
+pm_status pm_batch_output_dev(pm_batch *b, const double **out);
+
+/* Packets of the current set and the number of doubles of its output. */
+int64_t pm_batch_packets(const pm_batch *b);
+int64_t pm_batch_output_doubles(const pm_batch *b);
+
+const char *pm_batch_last_error(const pm_batch *b);
+
 /* Numerics helpers (PARAMENT library section: e.g. a different maximum
  * degree).  max_taylor_degree in [1, PM_MAX_TAYLOR_DEGREE] caps the degree
  * the planner may pick (default PM_MAX_TAYLOR_DEGREE); force_s >= 0 fixes the

@@ -44,6 +44,16 @@ SIGNATURES = {
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pm_fidelity_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                         ctypes.c_void_p, _c_double_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int]),
+    "pm_batch_destroy": (ctypes.c_int, [ctypes.c_void_p]),
+    "pm_batch_set": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "pm_batch_set_chunk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int64]),
+    "pm_batch_run": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_batch_result": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64]),
+    "pm_batch_output_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)]),
+    "pm_batch_packets": (ctypes.c_int64, [ctypes.c_void_p]),
+    "pm_batch_output_doubles": (ctypes.c_int64, [ctypes.c_void_p]),
+    "pm_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "pm_set_expm_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "pm_set_chunk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -254,6 +264,92 @@ class Context:
                                     ctypes.c_void_p(grad_t.data_ptr()),
                                     ctypes.c_void_p(U_t.data_ptr()) if U_t is not None else None,
                                     ctypes.c_void_p(stream.cuda_stream)), self._h)
+
+
+class _Instance(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int64), ("n_ctrl", ctypes.c_int64), ("order", ctypes.c_int),
+                ("H0", ctypes.c_void_p), ("Hk", ctypes.c_void_p), ("samples", ctypes.c_void_p),
+                ("n_samples", ctypes.c_int64), ("dt", ctypes.c_double)]
+
+
+class Batch:
+    """Many independent instances propagated by one persistent launch.
+
+    Each instance is anything with attributes H0, Hk, samples, h (slice
+    width) and order (e.g. a ``synth.Workload``)."""
+
+    def __init__(self, device: int = 0, precision: int = PM_FP64):
+        if isinstance(precision, str):
+            precision = PRECISIONS[precision]
+        h = ctypes.c_void_p()
+        st = _lib.pm_batch_create(ctypes.byref(h), device, precision)
+        if st != 0:
+            raise ParamentError(st, "pm_batch_create")
+        self._h = h
+        self.precision = precision
+        self.dims = []
+
+    def _check(self, st):
+        if st != 0:
+            raise ParamentError(st, _lib.pm_batch_last_error(self._h).decode())
+
+    def close(self):
+        if self._h:
+            _lib.pm_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    def __enter__(self):
+        return self
+
+    def __exit__(self, *a):
+        self.close()
+
+    def set_chunk(self, dim_class: int, chunk: int):
+        self._check(_lib.pm_batch_set_chunk(self._h, dim_class, chunk))
+
+    def set(self, instances):
+        keep = []
+        arr = (_Instance * len(instances))()
+        dims = []
+        for i, w in enumerate(instances):
+            H0 = _as_c128(w.H0)
+            d = H0.shape[0]
+            Hk = _as_c128(w.Hk).reshape(-1, d, d)
+            c = np.ascontiguousarray(np.asarray(w.samples, np.float64))
+            if c.ndim == 1:
+                c = c[None]
+            K = Hk.shape[0]
+            keep += [H0, Hk, c]
+            arr[i] = _Instance(d, K, int(w.order), H0.ctypes.data, Hk.ctypes.data if K else None,
+                               c.ctypes.data if K else None, c.shape[1], float(w.h))
+            dims.append(d)
+        self._check(_lib.pm_batch_set(self._h, ctypes.cast(arr, ctypes.c_void_p), len(instances)))
+        self.dims = dims
+
+    @property
+    def n_packets(self) -> int:
+        return int(_lib.pm_batch_packets(self._h))
+
+    def run(self, stream=None):
+        """Enqueue the whole batch (default: the null stream)."""
+        s = None if stream is None else ctypes.c_void_p(stream.cuda_stream)
+        self._check(_lib.pm_batch_run(self._h, s))
+
+    def results(self):
+        n = int(_lib.pm_batch_output_doubles(self._h))
+        buf = np.zeros(n // 2, np.complex128)
+        self._check(_lib.pm_batch_result(self._h, _ptr(buf), n))
+        out, o = [], 0
+        for d in self.dims:
+            out.append(buf[o:o + d * d].reshape(d, d).copy())
+            o += d * d
+        return out
 
 
 def _make_function():

@@ -12,7 +12,7 @@ import sys
 HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libparament.so")
-SOURCES = ["parament.cpp", "engine_mfma.hip", "engine_valu.hip", "engine_grad.hip"]
+SOURCES = ["parament.cpp", "engine_mfma.hip", "engine_valu.hip", "engine_grad.hip", "engine_batch.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

@@ -47,7 +47,8 @@ struct Geo {
     static constexpr int LD = D + 1;     // padded LDS row stride
     static constexpr int PLANE = D * LD;
     static constexpr int SLOT = 2 * PLANE;   // in doubles (a float slot uses the front half)
-    static_assert(TW == 1 || NT == 1, "multi-wave teams own their whole block");
+    // Several multi-wave teams in one block synchronise block-wide, so they
+    // must run the same control flow (the batched engine's lockstep packets).
 };
 
 // Per-wave coordinates.

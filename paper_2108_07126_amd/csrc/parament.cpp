@@ -20,6 +20,8 @@ hipError_t launch_mfma(int D, int precision, const PropParams& p, hipStream_t st
 hipError_t launch_valu(int D, bool fp64, const PropParams& p, hipStream_t stream);
 int mfma_chains_per_block(int D);
 hipError_t launch_backward(int D, const GradParams& gp, double* grad_samples, hipStream_t stream);
+hipError_t launch_batch(int precision, const BatchParams& bp, int blocks, hipStream_t stream);
+hipError_t batch_setup(int precision);
 }  // namespace pm
 
 using cplx = std::complex<double>;
@@ -845,5 +847,316 @@ pm_status pm_fidelity_grad(pm_ctx* ctx, const double* samples, int64_t n_samples
     if (U_out) std::memcpy(U_out, U.data(), 16 * d * d);
     return PM_OK;
 }
+
+// ------------------------------------------------------------------ batches
+
+}  // extern "C"
+
+struct pm_batch {
+    int device = 0;
+    int precision = PM_FP64;
+    int64_t chunk_cfg[3] = {0, 0, 0};   // dimension classes 16, 32, 64
+    std::vector<pm::PropParams> inst;
+    std::vector<pm::BatchPacket> packets;
+    int64_t out_doubles = 0;
+    double* d_basis = nullptr;
+    double* d_samples = nullptr;
+    double* d_nodes = nullptr;
+    unsigned* d_counters = nullptr;
+    double* d_out = nullptr;
+    pm::PropParams* d_inst = nullptr;
+    pm::BatchPacket* d_packets = nullptr;
+    unsigned* d_queue = nullptr;
+    hipStream_t cap = nullptr;
+    hipGraph_t graph = nullptr;
+    hipGraphExec_t exec = nullptr;
+    int blocks = 0;
+    bool broken = false;
+    std::string err;
+};
+
+namespace {
+
+int class_of(int64_t dim) { return dim <= 16 ? 16 : (dim <= 32 ? 32 : 64); }
+int class_index(int D) { return D == 16 ? 0 : (D == 32 ? 1 : 2); }
+int64_t default_batch_chunk(int D) { return D == 16 ? 64 : (D == 32 ? 32 : 16); }
+
+pm_status bfail(pm_batch* b, pm_status s, const std::string& msg) {
+    b->err = msg;
+    return s;
+}
+
+pm_status bhip(pm_batch* b, hipError_t e, const char* where) {
+    b->broken = true;
+    b->err = std::string(where) + ": " + hipGetErrorString(e);
+    return PM_E_DEVICE;
+}
+
+void batch_free(pm_batch* b) {
+    if (b->exec) (void)hipGraphExecDestroy(b->exec);
+    if (b->graph) (void)hipGraphDestroy(b->graph);
+    b->exec = nullptr;
+    b->graph = nullptr;
+    dfree(b->d_basis);
+    dfree(b->d_samples);
+    dfree(b->d_nodes);
+    dfree(b->d_counters);
+    dfree(b->d_out);
+    dfree(b->d_inst);
+    dfree(b->d_packets);
+    dfree(b->d_queue);
+    b->inst.clear();
+    b->packets.clear();
+    b->out_doubles = 0;
+}
+
+template <typename P>
+hipError_t upload(P** dst, const void* src, size_t bytes) {
+    hipError_t e = hipMalloc((void**)dst, std::max<size_t>(bytes, 256));
+    if (e != hipSuccess) {
+        *dst = nullptr;
+        return e;
+    }
+    if (src && bytes) e = hipMemcpy(*dst, src, bytes, hipMemcpyHostToDevice);
+    return e;
+}
+
+}  // namespace
+
+extern "C" {
+
+pm_status pm_batch_create(pm_batch** out, int device, int precision) {
+    if (!out) return PM_E_INVALID_ARG;
+    *out = nullptr;
+    if (unit_roundoff(precision) < 0) return PM_E_INVALID_ARG;
+    int n = 0;
+    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
+        (void)hipGetLastError();
+        return PM_E_DEVICE;
+    }
+    if (device < 0 || device >= n) return PM_E_INVALID_ARG;
+    pm_batch* b = new (std::nothrow) pm_batch();
+    if (!b) return PM_E_OOM;
+    b->device = device;
+    b->precision = precision;
+    DeviceGuard g(device);
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
+        cus = 256;
+    b->blocks = cus;
+    if (pm::batch_setup(precision) != hipSuccess || hipStreamCreate(&b->cap) != hipSuccess) {
+        delete b;
+        return PM_E_DEVICE;
+    }
+    *out = b;
+    return PM_OK;
+}
+
+pm_status pm_batch_destroy(pm_batch* b) {
+    if (!b) return PM_OK;
+    {
+        DeviceGuard g(b->device);
+        (void)hipDeviceSynchronize();
+        batch_free(b);
+        if (b->cap) (void)hipStreamDestroy(b->cap);
+    }
+    delete b;
+    return PM_OK;
+}
+
+pm_status pm_batch_set_chunk(pm_batch* b, int dim_class, int64_t chunk) {
+    if (!b) return PM_E_INVALID_ARG;
+    if ((dim_class != 16 && dim_class != 32 && dim_class != 64) || chunk < 0)
+        return bfail(b, PM_E_INVALID_ARG, "dim_class in {16, 32, 64}, chunk >= 0");
+    b->chunk_cfg[class_index(dim_class)] = chunk;
+    return PM_OK;
+}
+
+pm_status pm_batch_set(pm_batch* b, const pm_instance* inst, int64_t n_inst) {
+    if (!b) return PM_E_INVALID_ARG;
+    if (b->broken) return bfail(b, PM_E_DEVICE, "batch unusable after a device error");
+    if (n_inst < 1 || !inst) return bfail(b, PM_E_INVALID_ARG, "need at least one instance");
+    std::vector<pm::PropParams> P((size_t)n_inst);
+    std::vector<double> hbasis, hsamples;
+    std::vector<int64_t> boff(n_inst), soff(n_inst), noff(n_inst), coff(n_inst), ooff(n_inst);
+    std::vector<pm::BatchPacket> packets;
+    int64_t nodes_d = 0, counters_n = 0, out_d = 0;
+    for (int64_t i = 0; i < n_inst; ++i) {
+        const pm_instance& q = inst[i];
+        const std::string tag = "instance " + std::to_string(i) + ": ";
+        if (q.dim < 1 || q.dim > PM_MAX_DIM) return bfail(b, PM_E_INVALID_ARG, tag + "dim must be in [1, 64]");
+        if (q.n_ctrl < 0 || q.n_ctrl > pm::kMaxCtrl) return bfail(b, PM_E_INVALID_ARG, tag + "n_ctrl in [0, 8]");
+        if (q.order != 2 && q.order != 4) return bfail(b, PM_E_INVALID_ARG, tag + "order must be 2 or 4");
+        if (!q.H0 || (q.n_ctrl > 0 && (!q.Hk || !q.samples))) return bfail(b, PM_E_INVALID_ARG, tag + "null pointer");
+        if (!(q.dt > 0.0) || !std::isfinite(q.dt)) return bfail(b, PM_E_INVALID_ARG, tag + "dt must be finite and > 0");
+        if ((q.order == 2 && q.n_samples < 1) || (q.order == 4 && (q.n_samples < 3 || q.n_samples % 2 == 0)))
+            return bfail(b, PM_E_INVALID_ARG, tag + "bad n_samples for the order");
+        for (int64_t k = 0; k < q.n_ctrl * q.n_samples; ++k)
+            if (!std::isfinite(q.samples[k])) return bfail(b, PM_E_INVALID_ARG, tag + "non-finite sample");
+        std::vector<Mat> basis;
+        std::vector<std::pair<int, int>> pairs;
+        std::string err;
+        pm_status st = build_basis(q.dim, q.H0, q.n_ctrl, q.Hk, q.order, &basis, &pairs, &err);
+        if (st != PM_OK) return bfail(b, st, tag + err);
+        const int M = (int)basis.size();
+        const int D = class_of(q.dim);
+        pm::EngineInfo e;
+        pm::pick_engine(D, b->precision, &e);
+        std::vector<double> flat((size_t)M * q.dim * q.dim * 2);
+        for (int m = 0; m < M; ++m)
+            for (int64_t x = 0; x < q.dim * q.dim; ++x) {
+                flat[((size_t)m * q.dim * q.dim + x) * 2 + 0] = basis[m][x].real();
+                flat[((size_t)m * q.dim * q.dim + x) * 2 + 1] = basis[m][x].imag();
+            }
+        std::vector<double> lay((size_t)pm::basis_layout_doubles(e, M));
+        pm::basis_to_layout(e, M, (int)q.dim, flat.data(), lay.data());
+        boff[i] = (int64_t)hbasis.size();
+        hbasis.insert(hbasis.end(), lay.begin(), lay.end());
+        soff[i] = (int64_t)hsamples.size();
+        if (q.n_ctrl > 0) hsamples.insert(hsamples.end(), q.samples, q.samples + q.n_ctrl * q.n_samples);
+        const int64_t N = n_slices_of(q.order, q.n_samples);
+        const int TEAMS = pm::batch_teams(D);
+        int64_t chunk = b->chunk_cfg[class_index(D)];
+        if (chunk <= 0) chunk = default_batch_chunk(D);
+        chunk = std::min(chunk, N);
+        const int64_t chains = (N + chunk - 1) / chunk;
+        const int64_t npk = (chains + TEAMS - 1) / TEAMS;
+        noff[i] = nodes_d;
+        nodes_d += (2 * npk + 64) * (int64_t)D * D * 2;
+        coff[i] = counters_n;
+        counters_n += 2 * npk + 64;
+        ooff[i] = out_d;
+        out_d += q.dim * q.dim * 2;
+        pm::PropParams& p = P[i];
+        std::memset(&p, 0, sizeof(p));
+        p.n_samples = q.n_samples;
+        p.n_slices = N;
+        p.chunk = chunk;
+        p.n_chains = chains;
+        p.n_leaves = npk;
+        p.h = q.dt;
+        fill_theta(p.theta, b->precision, N);
+        p.K = (int)q.n_ctrl;
+        p.M = M;
+        p.order = q.order;
+        p.du = (int)q.dim;
+        p.max_degree = PM_MAX_TAYLOR_DEGREE;
+        p.force_s = -1;
+        for (size_t x = 0; x < pairs.size(); ++x) {
+            const int m = 1 + 2 * (int)q.n_ctrl + (int)x;
+            p.pair_a[m] = (uint8_t)pairs[x].first;
+            p.pair_b[m] = (uint8_t)pairs[x].second;
+        }
+        for (int64_t pk = 0; pk < npk; ++pk) {
+            pm::BatchPacket bp;
+            bp.inst = (int)i;
+            bp.D = D;
+            bp.chain0 = pk * TEAMS;
+            bp.nchains = (int)std::min<int64_t>(TEAMS, chains - bp.chain0);
+            bp.leaf = (int)pk;
+            bp.steps = std::min(chunk, N - bp.chain0 * chunk);
+            packets.push_back(bp);
+        }
+    }
+    // longest first: a block's work per packet ~ steps * teams * D^3
+    auto cost = [](const pm::BatchPacket& x) {
+        return (double)x.steps * pm::batch_teams(x.D) * (double)x.D * x.D * x.D;
+    };
+    std::stable_sort(packets.begin(), packets.end(),
+                     [&](const pm::BatchPacket& a, const pm::BatchPacket& c) { return cost(a) > cost(c); });
+
+    DeviceGuard g(b->device);
+    if (!g.ok) return bhip(b, hipErrorInvalidDevice, "hipSetDevice");
+    hipError_t he = hipDeviceSynchronize();
+    if (he != hipSuccess) return bhip(b, he, "hipDeviceSynchronize");
+    batch_free(b);
+    he = upload(&b->d_basis, hbasis.data(), hbasis.size() * sizeof(double));
+    if (he == hipSuccess) he = upload(&b->d_samples, hsamples.data(), hsamples.size() * sizeof(double));
+    if (he == hipSuccess) he = upload(&b->d_nodes, nullptr, (size_t)nodes_d * sizeof(double));
+    if (he == hipSuccess) he = upload(&b->d_counters, nullptr, (size_t)counters_n * sizeof(unsigned));
+    if (he == hipSuccess) he = hipMemset(b->d_counters, 0, std::max<size_t>((size_t)counters_n * sizeof(unsigned), 256));
+    if (he == hipSuccess) he = upload(&b->d_out, nullptr, (size_t)out_d * sizeof(double));
+    if (he == hipSuccess) he = upload(&b->d_queue, nullptr, sizeof(unsigned));
+    if (he != hipSuccess) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return bfail(b, PM_E_OOM, "device allocation for the batch failed");
+    }
+    for (int64_t i = 0; i < n_inst; ++i) {
+        pm::PropParams& p = P[i];
+        p.basis = b->d_basis + boff[i];
+        p.samples = b->d_samples + soff[i];
+        p.nodes = b->d_nodes + noff[i];
+        p.counters = b->d_counters + coff[i];
+        p.U_out = b->d_out + ooff[i];
+    }
+    he = upload(&b->d_inst, P.data(), P.size() * sizeof(pm::PropParams));
+    if (he == hipSuccess) he = upload(&b->d_packets, packets.data(), packets.size() * sizeof(pm::BatchPacket));
+    if (he == hipSuccess) he = hipDeviceSynchronize();
+    if (he != hipSuccess) {
+        (void)hipGetLastError();
+        batch_free(b);
+        return bfail(b, PM_E_OOM, "device allocation for the batch failed");
+    }
+    b->inst = P;
+    b->packets = packets;
+    b->out_doubles = out_d;
+    b->err.clear();
+    return PM_OK;
+}
+
+pm_status pm_batch_run(pm_batch* b, void* stream) {
+    if (!b) return PM_E_INVALID_ARG;
+    if (b->broken) return bfail(b, PM_E_DEVICE, "batch unusable after a device error");
+    if (b->inst.empty()) return bfail(b, PM_E_NOT_READY, "pm_batch_set has not been called");
+    DeviceGuard g(b->device);
+    if (!g.ok) return bhip(b, hipErrorInvalidDevice, "hipSetDevice");
+    hipError_t he;
+    if (!b->exec) {
+        pm::BatchParams bp;
+        bp.inst = b->d_inst;
+        bp.packets = b->d_packets;
+        bp.n_packets = (int)b->packets.size();
+        bp.queue = b->d_queue;
+        he = hipStreamBeginCapture(b->cap, hipStreamCaptureModeThreadLocal);
+        if (he != hipSuccess) return bhip(b, he, "hipStreamBeginCapture");
+        he = pm::launch_batch(b->precision, bp, b->blocks, b->cap);
+        hipGraph_t gr = nullptr;
+        const hipError_t he2 = hipStreamEndCapture(b->cap, &gr);
+        if (he != hipSuccess) return bhip(b, he, "batch launch");
+        if (he2 != hipSuccess) return bhip(b, he2, "hipStreamEndCapture");
+        b->graph = gr;
+        he = hipGraphInstantiate(&b->exec, b->graph, nullptr, nullptr, 0);
+        if (he != hipSuccess) return bhip(b, he, "hipGraphInstantiate");
+    }
+    he = hipGraphLaunch(b->exec, (hipStream_t)stream);
+    if (he != hipSuccess) return bhip(b, he, "hipGraphLaunch");
+    return PM_OK;
+}
+
+pm_status pm_batch_result(pm_batch* b, double* U_out, int64_t n_doubles) {
+    if (!b || !U_out) return PM_E_INVALID_ARG;
+    if (b->inst.empty()) return bfail(b, PM_E_NOT_READY, "pm_batch_set has not been called");
+    if (n_doubles < b->out_doubles) return bfail(b, PM_E_INVALID_ARG, "output buffer too small");
+    DeviceGuard g(b->device);
+    hipError_t he = hipDeviceSynchronize();
+    if (he != hipSuccess) return bhip(b, he, "batch execution");
+    he = hipMemcpy(U_out, b->d_out, sizeof(double) * b->out_doubles, hipMemcpyDeviceToHost);
+    if (he != hipSuccess) return bhip(b, he, "hipMemcpy results");
+    return PM_OK;
+}
+
+pm_status pm_batch_output_dev(pm_batch* b, const double** out) {
+    if (!b || !out) return PM_E_INVALID_ARG;
+    if (b->inst.empty()) return bfail(b, PM_E_NOT_READY, "pm_batch_set has not been called");
+    *out = b->d_out;
+    return PM_OK;
+}
+
+int64_t pm_batch_packets(const pm_batch* b) { return b ? (int64_t)b->packets.size() : -1; }
+
+int64_t pm_batch_output_doubles(const pm_batch* b) { return b ? b->out_doubles : -1; }
+
+const char* pm_batch_last_error(const pm_batch* b) { return b ? b->err.c_str() : ""; }
 
 }  // extern "C"

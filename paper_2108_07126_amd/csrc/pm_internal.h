@@ -46,6 +46,26 @@ struct GradParams {
     double* gw;         // [N][M] dL / d w_{j,m}
 };
 
+// Batched instances: a packet is up to teams(D) consecutive chains of one
+// instance, run in lockstep by one block of the persistent batch kernel.
+struct BatchPacket {
+    int inst;          // instance index
+    int D;             // 16, 32 or 64
+    int nchains;       // chains in the packet (the rest of the block's teams idle)
+    int leaf;          // packet index within its instance = leaf of the instance's tree
+    int64_t chain0;    // first chain; team t runs chain chain0 + t
+    int64_t steps;     // slices of the packet's longest chain
+};
+
+struct BatchParams {
+    const PropParams* inst;      // device array, one record per instance
+    const BatchPacket* packets;  // in execution order
+    int n_packets;
+    unsigned* queue;             // next packet; zeroed before every launch
+};
+
+constexpr int batch_teams(int D) { return D == 16 ? 16 : (D == 32 ? 4 : 1); }
+
 // Engines.  D is the (padded) engine dimension.
 //   MFMA engine: D in {16, 32, 64}; one team of (D/16)^2 waves per slice
 //   chain, every wave owning one 16x16 output tile.
