@@ -192,6 +192,14 @@ int64_t pm_batch_output_doubles(const pm_batch *b);
 
 const char *pm_batch_last_error(const pm_batch *b);
 
+/* Process-wide tuning (normally loaded from the autotuner's table):
+ * key "chains": the number of slice chains the automatic chunking aims for on
+ * engine class dim_class (2, 4, 16, 32, 64) in `precision`;
+ * key "batch_chunk": slices per chain of batched instances of class 16, 32
+ * or 64 in `precision`.  value 0 restores the built-in default.  Not
+ * thread-safe; set before propagating. */
+pm_status pm_tuning_set(const char *key, int dim_class, int precision, int64_t value);
+
 /* Numerics helpers (PARAMENT library section: e.g. a different maximum
  * degree).  max_taylor_degree in [1, PM_MAX_TAYLOR_DEGREE] caps the degree
  * the planner may pick (default PM_MAX_TAYLOR_DEGREE); force_s >= 0 fixes the

@@ -1,7 +1,7 @@
 """Python binding of the MI355X parallel-in-time Schrodinger propagator.
 
 Argument marshalling only: every step of the propagation runs in the HIP
-library ``libparament.so`` (built in-tree by ``paper_2108_07126_amd.build``),
+library ``libparament.so`` (built in-tree by ``paper_2108_07126_amd/build.py``),
 reached through its C ABI (include/parament.h) with ctypes.  Importing this
 package fails loudly when the library has not been built; there is no other
 code path.
@@ -54,6 +54,7 @@ SIGNATURES = {
     "pm_batch_packets": (ctypes.c_int64, [ctypes.c_void_p]),
     "pm_batch_output_doubles": (ctypes.c_int64, [ctypes.c_void_p]),
     "pm_batch_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
+    "pm_tuning_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64]),
     "pm_set_expm_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "pm_set_chunk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -73,7 +74,7 @@ def _load():
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "
-            "(python -m paper_2108_07126_amd.build)")
+            "(python paper_2108_07126_amd/build.py)")
     lib = ctypes.CDLL(LIB_PATH)
     for name, (res, args) in SIGNATURES.items():
         fn = getattr(lib, name)
@@ -83,6 +84,27 @@ def _load():
 
 
 _lib = _load()
+
+TUNING_PATH = os.path.join(_HERE, "tuning.txt")
+
+
+def load_tuning(path: str = TUNING_PATH) -> int:
+    """Apply an autotuner table (lines: key dim_class precision value)."""
+    if not os.path.exists(path):
+        return 0
+    n = 0
+    with open(path) as f:
+        for line in f:
+            line = line.split("#", 1)[0].split()
+            if len(line) != 4:
+                continue
+            key, dc, prec, val = line[0], int(line[1]), int(line[2]), int(line[3])
+            if _lib.pm_tuning_set(key.encode(), dc, prec, val) == 0:
+                n += 1
+    return n
+
+
+load_tuning()
 
 
 class ParamentError(RuntimeError):

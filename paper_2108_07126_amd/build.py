@@ -1,7 +1,9 @@
 """Build the HIP library libparament.so in-tree for gfx950.
 
-``python -m paper_2108_07126_amd.build`` (or ``build()``) compiles every
+``python paper_2108_07126_amd/build.py`` (or ``build()``) compiles every
 source under csrc/ with hipcc into paper_2108_07126_amd/libparament.so.
+Run it as a script or load it by path: importing the package loads the
+library, which may not exist yet.
 """
 from __future__ import annotations
 

@@ -314,9 +314,29 @@ pm_status check_prop_args(pm_ctx* ctx, int64_t n_samples, double dt) {
     return PM_OK;
 }
 
-// Chain length: about one chain per resident wave team, in whole units.
-int64_t auto_chunk(const pm::EngineInfo& e, int64_t N) {
-    const int64_t target = (int64_t)e.resident_chains;
+// Process-wide tuning table (pm_tuning_set): target chain counts of the
+// automatic chunking per engine class and precision, and batch chain lengths.
+int64_t g_tune_chains[5][4] = {};
+int64_t g_tune_batch_chunk[3][4] = {};
+
+int tune_class(int D) {
+    switch (D) {
+        case 2: return 0;
+        case 4: return 1;
+        case 16: return 2;
+        case 32: return 3;
+        case 64: return 4;
+        default: return -1;
+    }
+}
+
+// Chain length: about one chain per resident wave team (or the tuned count),
+// in whole units.
+int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision) {
+    int64_t target = (int64_t)e.resident_chains;
+    const int tc = tune_class(e.D);
+    if (tc >= 0 && precision >= 0 && precision < 4 && g_tune_chains[tc][precision] > 0)
+        target = g_tune_chains[tc][precision];
     int64_t c = (N + target - 1) / target;
     if (c < 1) c = 1;
     const int64_t u = e.chunk_unit;
@@ -327,7 +347,7 @@ int64_t auto_chunk(const pm::EngineInfo& e, int64_t N) {
 pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, const double* basis, const double* d_samples,
                   int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out) {
     const int64_t N = n_slices_of(ctx->order, n_samples);
-    int64_t chunk = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N);
+    int64_t chunk = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N, ctx->precision);
     chunk = ((chunk + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
     const int64_t chains = (N + chunk - 1) / chunk;
     const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
@@ -1017,6 +1037,7 @@ pm_status pm_batch_set(pm_batch* b, const pm_instance* inst, int64_t n_inst) {
         const int64_t N = n_slices_of(q.order, q.n_samples);
         const int TEAMS = pm::batch_teams(D);
         int64_t chunk = b->chunk_cfg[class_index(D)];
+        if (chunk <= 0) chunk = g_tune_batch_chunk[class_index(D)][b->precision];
         if (chunk <= 0) chunk = default_batch_chunk(D);
         chunk = std::min(chunk, N);
         const int64_t chains = (N + chunk - 1) / chunk;
@@ -1158,5 +1179,22 @@ int64_t pm_batch_packets(const pm_batch* b) { return b ? (int64_t)b->packets.siz
 int64_t pm_batch_output_doubles(const pm_batch* b) { return b ? b->out_doubles : -1; }
 
 const char* pm_batch_last_error(const pm_batch* b) { return b ? b->err.c_str() : ""; }
+
+pm_status pm_tuning_set(const char* key, int dim_class, int precision, int64_t value) {
+    if (!key || value < 0 || precision < 0 || precision > 3) return PM_E_INVALID_ARG;
+    const std::string k(key);
+    if (k == "chains") {
+        const int tc = tune_class(dim_class);
+        if (tc < 0) return PM_E_INVALID_ARG;
+        g_tune_chains[tc][precision] = value;
+        return PM_OK;
+    }
+    if (k == "batch_chunk") {
+        if (dim_class != 16 && dim_class != 32 && dim_class != 64) return PM_E_INVALID_ARG;
+        g_tune_batch_chunk[class_index(dim_class)][precision] = value;
+        return PM_OK;
+    }
+    return PM_E_INVALID_ARG;
+}
 
 }  // extern "C"

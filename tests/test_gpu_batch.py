@@ -41,7 +41,8 @@ def tol(prec, n, d, s=0):
         return 1e-10
     if prec == 3:
         return (16 * math.sqrt(n) * math.sqrt(d) * 2.0 ** -16 + 1e-4) * 2 ** s
-    return (4 * math.sqrt(n) * d * 2.0 ** -24 + 1e-6) * 2 ** s
+    c3m = 2.0 if prec == 2 else 1.0   # 3M: imaginary parts on the (|Ar|+|Ai|)(|Br|+|Bi|) scale
+    return (4 * math.sqrt(n) * d * 2.0 ** -24 * c3m + 1e-6) * 2 ** s
 
 
 def max_squarings(pm, w, prec):

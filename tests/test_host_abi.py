@@ -154,3 +154,20 @@ def test_create_without_device_reports_device_error():
     else:
         assert pm.STATUS[st] == "PM_E_DEVICE"
     assert pm.STATUS[pm._lib.pm_create(ctypes.byref(h), 0, 7)] == "PM_E_INVALID_ARG"
+
+
+def test_tuning_set_validation(tmp_path):
+    """pm_tuning_set accepts the documented keys and classes only; the table
+    loader applies well-formed lines and skips the rest."""
+    lib = pm._lib
+    assert lib.pm_tuning_set(b"chains", 16, 0, 0) == 0
+    assert lib.pm_tuning_set(b"chains", 8, 0, 128) == 1
+    assert lib.pm_tuning_set(b"chains", 16, 4, 128) == 1
+    assert lib.pm_tuning_set(b"chains", 16, 0, -1) == 1
+    assert lib.pm_tuning_set(b"batch_chunk", 2, 0, 32) == 1
+    assert lib.pm_tuning_set(b"batch_chunk", 32, 1, 0) == 0
+    assert lib.pm_tuning_set(b"unknown", 16, 0, 1) == 1
+    t = tmp_path / "tuning.txt"
+    t.write_text("# comment\nchains 16 0 0\nbatch_chunk 64 2 0  # default\nchains 7 0 5\nbad line\n")
+    assert pm.load_tuning(str(t)) == 2
+    pm.load_tuning()  # restore the shipped table, if any
