@@ -8,8 +8,17 @@ resident in HBM, through the C ABI's device entry point.
 
 Prints ONE JSON line.  Besides the headline (FP64 steps/s = slices/s), the
 line carries the roofline of the propagation kernel (timed with HIP events on
-the launch stream), the oracle's CPU rate, the FP32 path's rate and error,
-the fixed-error comparison FP64 vs FP32, and a per-slice-output variant.
+the launch stream), the oracle's CPU rate, and one object per leg:
+  precisions   every precision mode on the headline workload
+  slices       the headline workload with every U_j written to HBM
+  d64          the dim-64 precision sweep (2^16 slices), every mode, MFMA roofline
+  small        dims 2, 4 and 8 with per-slice output (HBM roofline)
+  grad         fidelity-gradient evals/s on the 3-qubit register
+  batch        512 uneven instances in one graph-captured launch
+  cpu          the oracle's rate and every mode's error against it
+  fixed_error  smallest N reaching a target U(T) error, FP64 vs mixed
+``--legs`` picks a subset (default: all); ``--legs copy`` adds a plain
+1 GiB device copy, the calibration kernel for the HBM byte counters.
 """
 from __future__ import annotations
 
@@ -29,10 +38,25 @@ METRIC = "steps/sec at fixed U(T) error, FP64 vs mixed precision; fidelity-grad 
 PEAK_FP64_TFLOPS = 78.6
 PEAK_FP32_TFLOPS = 157.3
 PEAK_HBM_GBS = 8000.0
+PEAK_BF16_TFLOPS = 2500.0
+PEAK = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "fp32_3m": PEAK_FP32_TFLOPS,
+        "bf16_split": PEAK_BF16_TFLOPS}
+# HBM bytes per launch of the headline kernel from the FETCH_SIZE/WRITE_SIZE
+# passes (scaled by a 1 GiB copy: 2.0 x FETCH_SIZE KiB, 1.0 x WRITE_SIZE KiB),
+# valid only while the kernel's sources hash to the value they had then.
+TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_tiles.h", "mfma_tree.h", "engine_common.h", "pm_internal.h"]
+MEASURED_TRAFFIC = {"bytes": (2.0 * 4430.421875 + 1.0 * 4139.90625) * 1024.0,
+                    "sources_sha256": "dfe9645af67c6a663dabf87bdb4596e8fe1e8e8fc7bd0c20bf0f55dbeb3cf185",
+                    "profile": "profiles/propagate_d16_random_qudit_traffic.md"}
+LEGS = ["precisions", "slices", "d64", "small", "grad", "batch", "cpu", "fixed_error"]
 
 
 def taylor_products(m: int) -> int:
     return 0 if m <= 1 else (1 if m == 2 else m // 2 + 1)
+
+
+def engine_dim(d: int) -> int:
+    return d if d <= 4 else (16 if d <= 16 else (32 if d <= 32 else 64))
 
 
 def algorithmic_flops(pm, w, precision, n_leaves: int) -> float:
@@ -41,8 +65,7 @@ def algorithmic_flops(pm, w, precision, n_leaves: int) -> float:
     the s squarings and the chain product, plus 4 M d^2 for the expand; the
     tree adds (n_leaves - 1) products.  (m, s) per slice come from the
     library's planner on ||G_j||_1."""
-    d = w.dim
-    D = 16 if 4 < d <= 16 else (32 if 16 < d <= 32 else (64 if d > 32 else d))
+    D = engine_dim(w.dim)
     B, _ = pm.build_basis_host(w.H0, w.Hk, w.order)
     M = B.shape[0]
     n = w.n_slices
@@ -68,10 +91,19 @@ def algorithmic_flops(pm, w, precision, n_leaves: int) -> float:
         G = np.tensordot(Wt[c0:c0 + 8192], B, axes=1)
         nu = np.max(np.sum(np.abs(G), axis=1), axis=1)
         for x in nu:
-            m, s = pm.plan_expm(float(x), 0 if precision == 0 else 1, n_slices=n)
+            m, s = pm.plan_expm(float(x), precision, n_slices=n)
             prods += taylor_products(m) + s + 1
     prods += n_leaves - 1
     return 8.0 * D ** 3 * prods + 4.0 * M * D * D * n
+
+
+def headline_traffic():
+    import hashlib
+    h = hashlib.sha256()
+    for f in TRAFFIC_SOURCES:
+        with open(os.path.join(ROOT, "paper_2108_07126_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return MEASURED_TRAFFIC["bytes"] if h.hexdigest() == MEASURED_TRAFFIC["sources_sha256"] else None
 
 
 def time_launches(fn, steps: int, warmup: int):
@@ -105,11 +137,88 @@ def blas_threads() -> int:
     return os.cpu_count() or 1
 
 
+def mode_list(pm):
+    return [("fp64", pm.PM_FP64), ("fp32", pm.PM_FP32), ("fp32_3m", pm.PM_FP32_3M),
+            ("bf16_split", pm.PM_BF16_SPLIT)]
+
+
+def flops_of(pm, ctx, w, precision) -> float:
+    _, chains, _ = ctx.launch_shape(w.n_samples)
+    return algorithmic_flops(pm, w, precision, chains)
+
+
+def leg_d64(pm, torch, dev, args, out):
+    """The dim-64 precision sweep: GUE H0 of norm 10 + 2 controls, 2^16
+    slices, midpoint rule; every mode against its own MFMA peak."""
+    import synth
+    w = synth.precision_sweep()
+    s_dev = torch.from_numpy(w.samples).to(dev)
+    res = {"workload": "precision_sweep_d64_K2_N65536_h1e-2_midpoint"}
+    Ug = {}
+    for name, prec in mode_list(pm):
+        ctx = pm.Context(0, prec)
+        ctx.set_hamiltonian(w.H0, w.Hk, w.order)
+        U = torch.zeros((64, 64), dtype=torch.complex128, device=dev)
+        wall, k = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U), max(3, args.steps // 4), 2)
+        fl = flops_of(pm, ctx, w, prec)
+        ach = fl / (k * 1e-3) / 1e12
+        res[name] = {"steps_per_s": w.n_slices / (wall * 1e-3), "ms_per_step": wall, "kernel_ms": k,
+                     "algorithmic_flop_per_launch": fl, "achieved_tflops": ach, "peak_tflops": PEAK[name],
+                     "frac": ach / PEAK[name], "launch_shape": list(ctx.launch_shape(w.n_samples))}
+        Ug[name] = U.cpu().numpy()
+        ctx.close()
+    out["d64"] = res
+    return w, Ug
+
+
+def leg_small(pm, torch, dev, args, out):
+    """Dims 2, 4 and 8 with every U_j written out: HBM-bound.  Algorithmic
+    bytes per slice = the slice's control samples (8 B each) + its
+    propagator (d^2 complex entries, 16 B in FP64 and 8 B otherwise)."""
+    import synth
+    cases = [("driven_qubit_d2_N2^26", synth.driven_qubit(n_slices=2 ** 26, h=0.01)),
+             ("random_d4_K2_N2^24", synth.random_system(4, 2, n_slices=2 ** 24, h=0.01, order=2, tag=40)),
+             ("qubit_register_d8_K4_N2^22", synth.qubit_register(n_slices=2 ** 22))]
+    res = {}
+    for label, w in cases:
+        d, N = w.dim, w.n_slices
+        s_dev = torch.from_numpy(w.samples).to(dev)
+        row = {}
+        for name, prec in (("fp64", pm.PM_FP64), ("fp32", pm.PM_FP32)):
+            ctx = pm.Context(0, prec)
+            ctx.set_hamiltonian(w.H0, w.Hk, w.order)
+            U = torch.zeros((d, d), dtype=torch.complex128, device=dev)
+            ct = torch.complex128 if prec == pm.PM_FP64 else torch.complex64
+            sl = torch.empty((N, d, d), dtype=ct, device=dev)
+            wall, k = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U, sl), 5, 2)
+            _, k_nos = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U), 5, 2)
+            nbytes = w.samples.size * 8 + N * d * d * (16 if prec == pm.PM_FP64 else 8)
+            gbs = nbytes / (k * 1e-3) / 1e9
+            row[name] = {"steps_per_s": N / (wall * 1e-3), "kernel_ms": k, "kernel_ms_without_slices": k_nos,
+                         "algorithmic_bytes": nbytes, "achieved_gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
+            del sl
+            ctx.close()
+        res[label] = row
+    out["small"] = res
+
+
+def leg_copy(torch, dev, out):
+    """A plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB): the
+    calibration kernel for the FETCH_SIZE / WRITE_SIZE counters."""
+    a = torch.empty(2 ** 27, dtype=torch.float64, device=dev).fill_(1.0)
+    b = torch.empty_like(a)
+    wall, k = time_launches(lambda: b.copy_(a), 5, 2)
+    out["copy"] = {"bytes_read": a.numel() * 8, "bytes_written": a.numel() * 8, "kernel_ms": k,
+                   "gbs": 2 * a.numel() * 8 / (k * 1e-3) / 1e9}
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=5)
+    ap.add_argument("--legs", default="all",
+                    help="comma list from " + ",".join(LEGS) + ",copy (default: all but copy)")
     ap.add_argument("--skip-cpu", action="store_true", help="leave out the oracle CPU baseline")
     ap.add_argument("--skip-fixed-error", action="store_true")
     ap.add_argument("--skip-batch", action="store_true")
@@ -119,6 +228,17 @@ def main():
               "(the time axis would shard across GPUs with one gather of block products).",
               file=sys.stderr)
         sys.exit(2)
+    legs = set(LEGS) if args.legs == "all" else set(x for x in args.legs.split(",") if x)
+    unknown = legs - set(LEGS) - {"copy"}
+    if unknown:
+        print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
+        sys.exit(2)
+    if args.skip_cpu:
+        legs -= {"cpu", "fixed_error"}
+    if args.skip_fixed_error:
+        legs.discard("fixed_error")
+    if args.skip_batch:
+        legs.discard("batch")
 
     import torch
     import paper_2108_07126_amd as pm
@@ -131,34 +251,19 @@ def main():
     d = w.dim
     s_dev = torch.from_numpy(w.samples).to(dev)
 
-    def make(precision):
-        ctx = pm.Context(0, precision)
-        ctx.set_hamiltonian(w.H0, w.Hk, w.order)
-        return ctx
-
-    modes = [("fp64", pm.PM_FP64), ("fp32", pm.PM_FP32), ("fp32_3m", pm.PM_FP32_3M),
-             ("bf16_split", pm.PM_BF16_SPLIT)]
-    ctxs, timing, Ug = {}, {}, {}
+    modes = mode_list(pm) if "precisions" in legs else mode_list(pm)[:1]
+    ctxs, timing, Ug, flops = {}, {}, {}, {}
     for name, prec in modes:
-        ctx = make(prec)
+        ctx = pm.Context(0, prec)
+        ctx.set_hamiltonian(w.H0, w.Hk, w.order)
         U = torch.zeros((d, d), dtype=torch.complex128, device=dev)
         steps = args.steps if name == "fp64" else max(5, args.steps // 2)
         timing[name] = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U), steps, args.warmup)
         Ug[name] = U.cpu().numpy()
         ctxs[name] = ctx
+        flops[name] = flops_of(pm, ctx, w, prec)
     wall64, k64 = timing["fp64"]
-
-    # per-slice output variant: 512 MiB of complex128 propagators per step
-    sl = torch.empty((N, d, d), dtype=torch.complex128, device=dev)
-    U64 = torch.zeros((d, d), dtype=torch.complex128, device=dev)
-    wall64s, k64s = time_launches(lambda: ctxs["fp64"].equiprop_dev(s_dev, w.h, U64, sl),
-                                  max(5, args.steps // 2), 2)
-    del sl
-
-    # leaves used by the automatic chunking (same rule as the library)
-    chunk = max(1, math.ceil(N / (256 * 8)))
-    leaves = math.ceil(N / chunk)
-    flops = {name: algorithmic_flops(pm, w, 0 if name == "fp64" else 1, leaves) for name, _ in modes}
+    chunk, chains, leaves = ctxs["fp64"].launch_shape(w.n_samples)
     ach64 = flops["fp64"] / (k64 * 1e-3) / 1e12
 
     out = {
@@ -175,37 +280,61 @@ def main():
         "dtype": "f64",
         "data": "synthetic",
         "config": {"workload": "random_qudit_d16_K3_N131072_h1e-3_magnus4", "dim": d, "n_ctrl": w.n_ctrl,
-                   "n_slices": N, "order": 4, "dt": w.h, "output": "U(T)", "chunk": chunk, "leaves": leaves},
+                   "n_slices": N, "order": 4, "dt": w.h, "output": "U(T)", "chunk": chunk, "chains": chains,
+                   "leaves": leaves},
         "roofline": {"bound": "mfma", "achieved": ach64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
-                     "frac": ach64 / PEAK_FP64_TFLOPS, "traffic": None,
+                     "frac": ach64 / PEAK_FP64_TFLOPS, "traffic": headline_traffic(),
+                     "traffic_unit": "bytes per launch",
+                     "algorithmic_bytes_per_launch": w.samples.size * 8 + d * d * 16,
                      "kernel": "propagate_mfma<double,16,4,true,0>", "kernel_ms": k64,
                      "algorithmic_flop_per_launch": flops["fp64"]},
-        "precisions": {name: {"steps_per_s": N / (timing[name][0] * 1e-3), "ms_per_step": timing[name][0],
-                              "kernel_ms": timing[name][1],
-                              "achieved_tflops": flops[name] / (timing[name][1] * 1e-3) / 1e12}
-                       for name, _ in modes},
-        "fp64_with_slices": {"steps_per_s": N / (wall64s * 1e-3), "kernel_ms": k64s,
-                             "slice_bytes": N * d * d * 16,
-                             "hbm_write_gbs": N * d * d * 16 / (k64s * 1e-3) / 1e9},
     }
+    if "precisions" in legs:
+        out["precisions"] = {name: {"steps_per_s": N / (timing[name][0] * 1e-3), "ms_per_step": timing[name][0],
+                                    "kernel_ms": timing[name][1],
+                                    "achieved_tflops": flops[name] / (timing[name][1] * 1e-3) / 1e12,
+                                    "peak_tflops": PEAK[name]}
+                             for name, _ in modes}
 
-    # adjoint gradient: fidelity-grad evals/s on the 3-qubit register workload
-    wg = synth.qubit_register()
-    cg = pm.Context(0, pm.PM_FP64)
-    cg.set_hamiltonian(wg.H0, wg.Hk, 2)
-    sg = torch.from_numpy(wg.samples).to(dev)
-    Wt = torch.zeros((8, 8), dtype=torch.complex128, device=dev)
-    gt = torch.zeros_like(sg)
-    Ut = torch.zeros((8, 8), dtype=torch.complex128, device=dev)
-    loss, grad_h, Uh = cg.fidelity_grad(wg.samples, wg.h, wg.target)   # host entry point (also warms up)
-    g_tr = np.trace(wg.target.conj().T @ Uh)
-    Wt.copy_(torch.from_numpy(-(2 * g_tr / 64) * wg.target))
-    wall_g, k_g = time_launches(lambda: cg.backward_dev(sg, wg.h, Wt, gt, Ut), max(5, args.steps), 2)
-    out["grad"] = {"workload": "qubit_register_d8_K4_N4096", "evals_per_s": 1e3 / wall_g, "ms_per_eval": wall_g,
-                   "gpu_ms_per_eval": k_g, "params": int(wg.samples.size), "loss": loss}
+    if "slices" in legs:
+        # per-slice output: 512 MiB of complex128 propagators per step
+        sl = torch.empty((N, d, d), dtype=torch.complex128, device=dev)
+        U64 = torch.zeros((d, d), dtype=torch.complex128, device=dev)
+        wall64s, k64s = time_launches(lambda: ctxs["fp64"].equiprop_dev(s_dev, w.h, U64, sl),
+                                      max(5, args.steps // 2), 2)
+        del sl
+        out["fp64_with_slices"] = {"steps_per_s": N / (wall64s * 1e-3), "kernel_ms": k64s,
+                                   "slice_bytes": N * d * d * 16,
+                                   "hbm_write_gbs": N * d * d * 16 / (k64s * 1e-3) / 1e9}
 
-    # batched uneven instances: one persistent, graph-captured launch
-    if not args.skip_batch:
+    w64 = Ug64 = None
+    if "d64" in legs:
+        w64, Ug64 = leg_d64(pm, torch, dev, args, out)
+    if "small" in legs:
+        leg_small(pm, torch, dev, args, out)
+    if "copy" in legs:
+        leg_copy(torch, dev, out)
+
+    wg = None
+    if "grad" in legs:
+        # adjoint gradient: fidelity-grad evals/s on the 3-qubit register workload
+        wg = synth.qubit_register()
+        cg = pm.Context(0, pm.PM_FP64)
+        cg.set_hamiltonian(wg.H0, wg.Hk, 2)
+        sg = torch.from_numpy(wg.samples).to(dev)
+        Wt = torch.zeros((8, 8), dtype=torch.complex128, device=dev)
+        gt = torch.zeros_like(sg)
+        Ut = torch.zeros((8, 8), dtype=torch.complex128, device=dev)
+        loss, grad_h, Uh = cg.fidelity_grad(wg.samples, wg.h, wg.target)   # host entry point (also warms up)
+        g_tr = np.trace(wg.target.conj().T @ Uh)
+        Wt.copy_(torch.from_numpy(-(2 * g_tr / 64) * wg.target))
+        wall_g, k_g = time_launches(lambda: cg.backward_dev(sg, wg.h, Wt, gt, Ut), max(5, args.steps), 2)
+        out["grad"] = {"workload": "qubit_register_d8_K4_N4096", "evals_per_s": 1e3 / wall_g,
+                       "ms_per_eval": wall_g, "gpu_ms_per_eval": k_g, "params": int(wg.samples.size),
+                       "loss": loss}
+
+    if "batch" in legs:
+        # batched uneven instances: one persistent, graph-captured launch
         ws = synth.batched_instances()
         nsl = int(sum(x.n_slices for x in ws))
         bt = pm.Batch(0, pm.PM_FP32_3M)
@@ -215,11 +344,11 @@ def main():
         wall_b, k_b = time_launches(lambda: bt.run(torch.cuda.current_stream()), 3, 1)
         out["batch"] = {"workload": "512 uneven instances (d 2..64, K 1..4, N 1e3..1e5, orders 2/4)",
                         "precision": "fp32_3m", "slices": nsl, "packets": bt.n_packets, "ms_per_run": wall_b,
-                        "steps_per_s": nsl / (wall_b * 1e-3), "set_s": t_set}
+                        "kernel_ms": k_b, "steps_per_s": nsl / (wall_b * 1e-3), "set_s": t_set}
         bt.close()
 
     Uo = None
-    if not args.skip_cpu:
+    if "cpu" in legs:
         import oracle.propagator as orc
         t0 = time.perf_counter()
         Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, w.order)
@@ -227,11 +356,25 @@ def main():
         out["cpu_baseline"] = {"value": N / dt_cpu, "unit": "steps/s", "cores": blas_threads(), "kind": "oracle",
                                "sample": f"the whole workload ({N} slices, one run, {dt_cpu:.1f} s)"}
         out["error_vs_oracle"] = {name: orc.relative_frobenius(Ug[name], Uo) for name, _ in modes}
-        _, go = orc.control_gradient(wg.H0, wg.Hk, wg.samples, wg.h, 2,
-                                     orc.fidelity_grad_U(orc.propagate(wg.H0, wg.Hk, wg.samples, wg.h, 2), wg.target))
-        out["grad"]["rel_err_vs_oracle"] = float(np.max(np.abs(grad_h - go)) / np.max(np.abs(go)))
+        if wg is not None:
+            _, go = orc.control_gradient(wg.H0, wg.Hk, wg.samples, wg.h, 2,
+                                         orc.fidelity_grad_U(orc.propagate(wg.H0, wg.Hk, wg.samples, wg.h, 2),
+                                                             wg.target))
+            out["grad"]["rel_err_vs_oracle"] = float(np.max(np.abs(grad_h - go)) / np.max(np.abs(go)))
+        if w64 is not None:
+            # dim 64: error of U(T) on a bounded prefix (the oracle needs about
+            # 1.5 ms per slice at this size on the host)
+            n_pre = 4096
+            wp = synth.precision_sweep(n_slices=n_pre)
+            Uo64 = orc.propagate(wp.H0, wp.Hk, wp.samples, wp.h, wp.order)
+            e64 = {}
+            for name, prec in mode_list(pm):
+                with pm.Context(0, prec) as ctx:
+                    ctx.set_hamiltonian(wp.H0, wp.Hk, wp.order)
+                    e64[name] = orc.relative_frobenius(ctx.equiprop(wp.samples, wp.h), Uo64)
+            out["d64"]["error_vs_oracle_first_4096_slices"] = e64
 
-    if not args.skip_fixed_error and Uo is not None:
+    if "fixed_error" in legs and Uo is not None:
         import oracle.propagator as orc
         # same T, coarser slicing: smallest N=2^n meeting each target error
         T = N * w.h

@@ -210,6 +210,14 @@ pm_status pm_tuning_set(const char *key, int dim_class, int precision, int64_t v
 pm_status pm_set_expm_policy(pm_ctx *ctx, int max_taylor_degree, int force_s);
 pm_status pm_set_chunk(pm_ctx *ctx, int64_t chunk);
 
+/* The decomposition a propagation of n_samples samples would use on this
+ * context (after pm_set_hamiltonian; host-only, nothing is launched):
+ * *chunk slices per chain, *chains chains, *leaves leaves of the pairwise
+ * tree (chains are combined per block before the tree, so leaves <= chains).
+ * The reduction performs chains - 1 products after the chains. */
+pm_status pm_launch_shape(pm_ctx *ctx, int64_t n_samples, int64_t *chunk, int64_t *chains,
+                          int64_t *leaves);
+
 /* Human-readable name of a status code (static storage). */
 const char *pm_status_string(pm_status s);
 

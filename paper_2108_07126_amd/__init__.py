@@ -57,6 +57,8 @@ SIGNATURES = {
     "pm_tuning_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64]),
     "pm_set_expm_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "pm_set_chunk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "pm_launch_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
+                                       ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
     "pm_last_error": (ctypes.c_char_p, [ctypes.c_void_p]),
     "pm_basis_count": (ctypes.c_int64, [ctypes.c_int64, ctypes.c_int]),
@@ -224,6 +226,13 @@ class Context:
 
     def set_chunk(self, chunk: int = 0):
         _check(_lib.pm_set_chunk(self._h, chunk), self._h)
+
+    def launch_shape(self, n_samples: int) -> Tuple[int, int, int]:
+        """(chunk, chains, leaves) a propagation of n_samples would use."""
+        c, n, l = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_int64()
+        _check(_lib.pm_launch_shape(self._h, n_samples, ctypes.byref(c), ctypes.byref(n), ctypes.byref(l)),
+               self._h)
+        return c.value, n.value, l.value
 
     def equiprop(self, samples, dt: float, return_slices: bool = False):
         """U(T) (complex128) from host samples [n_ctrl][n_samples]; optionally all U_j."""

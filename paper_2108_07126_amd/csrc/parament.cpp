@@ -646,6 +646,20 @@ pm_status pm_set_chunk(pm_ctx* ctx, int64_t chunk) {
     return PM_OK;
 }
 
+pm_status pm_launch_shape(pm_ctx* ctx, int64_t n_samples, int64_t* chunk, int64_t* chains,
+                          int64_t* leaves) {
+    if (!ctx || !chunk || !chains || !leaves) return ctx ? fail(ctx, PM_E_INVALID_ARG, "null output") : PM_E_INVALID_ARG;
+    if (ctx->dim == 0) return fail(ctx, PM_E_NOT_READY, "pm_set_hamiltonian has not been called");
+    const int64_t N = n_slices_of(ctx->order, n_samples);
+    if (N < 1) return fail(ctx, PM_E_INVALID_ARG, "bad n_samples for the integrator order");
+    int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(ctx->eng, N, ctx->precision);
+    c = ((c + ctx->eng.chunk_unit - 1) / ctx->eng.chunk_unit) * ctx->eng.chunk_unit;
+    *chunk = c;
+    *chains = (N + c - 1) / c;
+    *leaves = (*chains + ctx->eng.chains_per_leaf - 1) / ctx->eng.chains_per_leaf;
+    return PM_OK;
+}
+
 pm_status pm_set_hamiltonian(pm_ctx* ctx, int64_t dim, const double* H0, int64_t n_ctrl,
                              const double* Hk, int order) {
     if (!ctx) return PM_E_INVALID_ARG;

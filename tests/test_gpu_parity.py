@@ -202,3 +202,19 @@ def test_device_entry_point_matches_host(pm):
         st.synchronize()
         assert np.array_equal(U.cpu().numpy(), Uh)
         assert np.array_equal(sl.cpu().numpy(), slh)
+
+
+def test_launch_shape_reports_decomposition(pm):
+    """pm_launch_shape reports the chunking a propagation uses: explicit
+    chunks are honoured, chains cover every slice once, leaves never exceed
+    chains, and the propagation at that shape is still exact."""
+    w = synth.random_qudit(n_slices=1000)
+    with pm.Context(0, pm.PM_FP64) as ctx:
+        ctx.set_hamiltonian(w.H0, w.Hk, w.order)
+        c, n, l = ctx.launch_shape(w.n_samples)
+        assert c >= 1 and n == -(-1000 // c) and 1 <= l <= n
+        ctx.set_chunk(7)
+        c, n, l = ctx.launch_shape(w.n_samples)
+        assert (c, n) == (7, 143) and l == 36
+        U = ctx.equiprop(w.samples, w.h)
+    assert orc.relative_frobenius(U, orc.propagate(w.H0, w.Hk, w.samples, w.h, w.order)) <= TOL64
