@@ -190,6 +190,8 @@ pm_status pm_batch_output_dev(pm_batch *b, const double **out);
 int64_t pm_batch_packets(const pm_batch *b);
 int64_t pm_batch_output_doubles(const pm_batch *b);
 
+/* Most recent failure on b; with b == NULL, why the calling thread's last
+ * pm_batch_create / pm_create failed. */
 const char *pm_batch_last_error(const pm_batch *b);
 
 /* Process-wide tuning (normally loaded from the autotuner's table):
@@ -222,7 +224,8 @@ pm_status pm_launch_shape(pm_ctx *ctx, int64_t n_samples, int64_t *chunk, int64_
 const char *pm_status_string(pm_status s);
 
 /* Description of the most recent failure on ctx ("" if none; static storage
- * owned by the context, valid until the next call on it). */
+ * owned by the context, valid until the next call on it).  With ctx == NULL:
+ * why the calling thread's last pm_create / pm_batch_create failed. */
 const char *pm_last_error(const pm_ctx *ctx);
 
 /* ---- host-only helpers: no GPU is touched ------------------------------ */
@@ -253,14 +256,18 @@ pm_status pm_slice_weights_host(int64_t n_ctrl, const double *samples,
                                 int64_t slice, double *weights_out);
 
 /* Truncation threshold theta_m of the degree-m Taylor polynomial used for a
- * propagation of n_slices slices: the largest theta with
- *     theta^(m+1)/(m+1)! / (1 - theta/(m+2)) <= u_t,
- * which bounds the remainder of exp(X) - T_m(X) for ||X|| <= theta, with the
- * truncation target u_t = max(2^-53, u / sqrt(n_slices)) and u the
- * precision's unit roundoff (2^-53 FP64, 2^-24 FP32 modes, 2^-16 BF16
- * split).  Truncation errors of neighbouring slices add coherently (~N u_t)
- * while rounding errors add like a random walk (~sqrt(N) u), hence the
- * sqrt(N) in the target.  n_slices >= 1. */
+ * propagation of n_slices slices.  With the remainder bound
+ *     R_m(theta) = theta^(m+1)/(m+1)! / (1 - theta/(m+2))
+ * of exp(X) - T_m(X) for ||X|| <= theta:
+ *   PM_FP64: the largest theta with R_m(theta) <= 2^-53;
+ *   reduced modes: the largest theta with R_m(theta) / theta <= u / sqrt(N),
+ *     u = 2^-24 (FP32 modes) or 2^-16 (BF16 split).  These modes carry each
+ *     slice propagator as I + E and accumulate the chain as Q + E Q, so
+ *     their rounding error per slice scales with ||E|| ~ ||G||; truncation
+ *     errors of neighbouring slices add coherently (~N) while rounding errors
+ *     add like a random walk (~sqrt(N)), hence the target relative to ||G||
+ *     with the sqrt(N).
+ * n_slices >= 1. */
 pm_status pm_taylor_theta(int m, int precision, int64_t n_slices, double *theta_out);
 
 /* The planner's choice for a slice with ||G||_1 = nu in a propagation of

@@ -185,7 +185,9 @@ class Context:
         if isinstance(precision, str):
             precision = PRECISIONS[precision]
         h = ctypes.c_void_p()
-        _check(_lib.pm_create(ctypes.byref(h), device, precision))
+        st = _lib.pm_create(ctypes.byref(h), device, precision)
+        if st != 0:
+            raise ParamentError(st, "pm_create: " + _lib.pm_last_error(None).decode())
         self._h = h
         self.precision = precision
         self.dim = None
@@ -315,7 +317,7 @@ class Batch:
         h = ctypes.c_void_p()
         st = _lib.pm_batch_create(ctypes.byref(h), device, precision)
         if st != 0:
-            raise ParamentError(st, "pm_batch_create")
+            raise ParamentError(st, "pm_batch_create: " + _lib.pm_batch_last_error(None).decode())
         self._h = h
         self.precision = precision
         self.dims = []

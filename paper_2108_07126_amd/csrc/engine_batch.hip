@@ -45,7 +45,9 @@ __device__ void run_packet(const BatchParams& bp, const BatchPacket& P, double* 
     const int64_t chain = P.chain0 + team;
     const int64_t j0 = active ? chain * p.chunk : 0;
     const int64_t j1 = active ? min(p.n_slices, j0 + p.chunk) : 0;
+    constexpr bool kF64 = std::is_same<T, double>::value;
     Tile<T> Q = ident<T>(L);
+    Tile<double> Qx = ident_as<T>(L);
     const WeightRecipe wr = weight_recipe(p, L.lane);
     const double lth = lane_theta_of(p, L.lane);
     SliceSamples smp = gather_samples(p, wr, j0);
@@ -85,21 +87,25 @@ __device__ void run_packet(const BatchParams& bp, const BatchPacket& P, double* 
             Gt.re[r] = (T)ldexp(gre[r], -s);
             Gt.im[r] = (T)ldexp(gim[r], -s);
         }
-        Tile<T> U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
-        if (s > 0) {
-            if constexpr (std::is_same<T, double>::value) {
-                U = square_n<G, double>(U, s, L, s0);
-            } else {
-                U = relayout<G, T>(square_n<G, double>(relayout<G, double>(U, s0, L), s, L, s0), s0, L);
-            }
+        if constexpr (kF64) {
+            Tile<T> U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
+            if (s > 0) U = square_n<G, double>(U, s, L, s0);
+            team_sync<G>();
+            slot_store<G, T>(s0, U, L);
+            slot_store<G, T>(s1, Q, L);
+            team_sync<G>();
+            Q = mulT<G, T, PMODE>(s0, s1, L);
+        } else {
+            // reduced modes: I + E slices, Q <- Q + E Q with Q in FP64
+            Tile<T> E = taylor_exp<G, T, PMODE, true>(Gt, m, L, s0, s1);
+            if (s > 0)
+                E = relayout<G, T>(square_excess_n<G>(relayout<G, double>(E, s0, L), s, L, s0), s0, L);
+            chain_acc<G, T, PMODE>(Qx, E, L, s0, s1);
         }
-        team_sync<G>();
-        slot_store<G, T>(s0, U, L);
-        slot_store<G, T>(s1, Q, L);
-        team_sync<G>();
-        Q = mulT<G, T, PMODE>(s0, s1, L);
     }
-    Tile<double> Qd = relayout<G, double>(Q, s0, L);
+    Tile<double> Qd;
+    if constexpr (kF64) Qd = Q;
+    else Qd = relayout_rows<G, T, double>(Qx, s0, L);
     if constexpr (TEAMS > 1) {
         for (int st = 1; st < TEAMS; st <<= 1) {
             __syncthreads();

@@ -65,7 +65,13 @@ propagate_mfma(PropParams p) {
     const int64_t chain = (int64_t)blockIdx.x * NT + team;
     const int64_t j0 = min(p.n_slices, chain * p.chunk);
     const int64_t j1 = min(p.n_slices, j0 + p.chunk);
+    constexpr bool kF64 = std::is_same<T, double>::value;
+    // FP64: the chain product in registers.  Reduced modes: slices as I + E
+    // (E accurate relative to ||G||) and the chain as Q <- Q + E Q with Q in
+    // FP64, so the rounding of the working precision never touches the
+    // identity part.
     Tile<T> Q = ident<T>(L);
+    Tile<double> Qx = ident_as<T>(L);
     // lane m < M gathers and combines the weight of basis matrix m; the next
     // slice's samples are loaded while this slice is exponentiated
     const WeightRecipe wr = weight_recipe(p, L.lane);
@@ -99,24 +105,27 @@ propagate_mfma(PropParams p) {
             Gt.re[r] = (T)ldexp(gre[r], -s);
             Gt.im[r] = (T)ldexp(gim[r], -s);
         }
-        // exponentiate
-        Tile<T> U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
-        if (s > 0) {
-            if constexpr (std::is_same<T, double>::value) {
-                U = square_n<G, double>(U, s, L, s0);
-            } else {
-                U = relayout<G, T>(square_n<G, double>(relayout<G, double>(U, s0, L), s, L, s0), s0, L);
-            }
+        if constexpr (kF64) {
+            // exponentiate, square, store, chain product Q <- U Q
+            Tile<T> U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
+            if (s > 0) U = square_n<G, double>(U, s, L, s0);
+            if (p.slices_out) store_slice<G, T>(p, j, U, L);
+            team_sync<G>();
+            slot_store<G, T>(s0, U, L);
+            slot_store<G, T>(s1, Q, L);
+            team_sync<G>();
+            Q = mulT<G, T, PMODE>(s0, s1, L);
+        } else {
+            Tile<T> E = taylor_exp<G, T, PMODE, true>(Gt, m, L, s0, s1);
+            if (s > 0)
+                E = relayout<G, T>(square_excess_n<G>(relayout<G, double>(E, s0, L), s, L, s0), s0, L);
+            if (p.slices_out) store_slice<G, T>(p, j, plus_ident<T>(E, L), L);
+            chain_acc<G, T, PMODE>(Qx, E, L, s0, s1);
         }
-        if (p.slices_out) store_slice<G, T>(p, j, U, L);
-        // chain product Q <- U Q
-        team_sync<G>();
-        slot_store<G, T>(s0, U, L);
-        slot_store<G, T>(s1, Q, L);
-        team_sync<G>();
-        Q = mulT<G, T, PMODE>(s0, s1, L);
     }
-    Tile<double> Qd = relayout<G, double>(Q, s0, L);
+    Tile<double> Qd;
+    if constexpr (kF64) Qd = Q;
+    else Qd = relayout_rows<G, T, double>(Qx, s0, L);
     if (p.chain_out && chain < p.n_chains)
         node_store<G>(p.chain_out + chain * (int64_t)G::D * G::D * 2, Qd, L);
     // one-wave teams of a block: combine their chains in LDS (later team on

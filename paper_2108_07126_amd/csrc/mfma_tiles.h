@@ -78,6 +78,28 @@ __device__ __forceinline__ Tile<T> ident(const Lane& L) {
     return t;
 }
 
+// The identity in the register layout of T-kernels, held as FP64 values
+// (the reduced-precision kernels keep their chain products this way).
+template <typename T>
+__device__ __forceinline__ Tile<double> ident_as(const Lane& L) {
+    Tile<double> t;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        t.re[r] = (16 * L.TI + crow<T>(L.g, r) == 16 * L.TJ + L.j) ? 1.0 : 0.0;
+        t.im[r] = 0.0;
+    }
+    return t;
+}
+
+template <typename T>
+__device__ __forceinline__ Tile<T> plus_ident(const Tile<T>& e, const Lane& L) {
+    Tile<T> t = e;
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if (16 * L.TI + crow<T>(L.g, r) == 16 * L.TJ + L.j) t.re[r] += T(1);
+    return t;
+}
+
 template <typename T>
 __device__ __forceinline__ void axpy(Tile<T>& y, double a, const Tile<T>& x) {
     const T ta = (T)a;
@@ -120,6 +142,35 @@ __device__ __forceinline__ Tile<Tdst> relayout(const Tile<Tsrc>& t, double* slot
             const int row = 16 * L.TI + crow<Tdst>(L.g, r);
             o.re[r] = (Tdst)re[row * G::LD + col];
             o.im[r] = (Tdst)im[row * G::LD + col];
+        }
+        return o;
+    }
+}
+
+// FP64 values moved from the row layout of LSrc-kernels to that of
+// LDst-kernels (through an LDS slot).
+template <class G, typename LSrc, typename LDst>
+__device__ __forceinline__ Tile<double> relayout_rows(const Tile<double>& t, double* slot, const Lane& L) {
+    if constexpr (std::is_same<LSrc, LDst>::value) {
+        return t;
+    } else {
+        double* re = slot;
+        double* im = slot + G::PLANE;
+        const int col = 16 * L.TJ + L.j;
+        team_sync<G>();
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * L.TI + crow<LSrc>(L.g, r);
+            re[row * G::LD + col] = t.re[r];
+            im[row * G::LD + col] = t.im[r];
+        }
+        team_sync<G>();
+        Tile<double> o;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * L.TI + crow<LDst>(L.g, r);
+            o.re[r] = re[row * G::LD + col];
+            o.im[r] = im[row * G::LD + col];
         }
         return o;
     }
@@ -300,10 +351,18 @@ __device__ __forceinline__ double team_norm1(const double* gre, const double* gi
 }
 
 // exp(-i G) for a (pre-scaled) Hermitian tile set by the degree-m Taylor
-// polynomial, split as C(Y) - i G S'(Y).  Uses slots s0, s1.
-template <class G, typename T, int PMODE = 0>
+// polynomial, split as C(Y) - i G S'(Y).  With EXCESS the identity term is
+// left out (the result is exp(-i G) - I, accurate relative to ||G||).  Uses
+// slots s0, s1.
+template <class G, typename T, int PMODE = 0, bool EXCESS = false>
 __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s0, double* s1) {
-    Tile<T> C = ident<T>(L);
+    Tile<T> C;
+    if constexpr (EXCESS) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) C.re[r] = C.im[r] = T(0);
+    } else {
+        C = ident<T>(L);
+    }
     Tile<T> S;
     if (m <= 1) {
         S = Gt;
@@ -362,6 +421,47 @@ __device__ __forceinline__ Tile<T> square_n(Tile<T> U, int s, const Lane& L, dou
         U = slot_mul<G, T>(s0, s0, L);
     }
     return U;
+}
+
+// E <- (I + E)^2 - I = 2E + E E, s times (FP64).
+template <class G>
+__device__ __forceinline__ Tile<double> square_excess_n(Tile<double> E, int s, const Lane& L, double* s0) {
+    for (int i = 0; i < s; ++i) {
+        team_sync<G>();
+        slot_store<G, double>(s0, E, L);
+        team_sync<G>();
+        const Tile<double> P = slot_mul<G, double>(s0, s0, L);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            E.re[r] = fma(2.0, E.re[r], P.re[r]);
+            E.im[r] = fma(2.0, E.im[r], P.im[r]);
+        }
+    }
+    return E;
+}
+
+// Chain step of the reduced-precision kernels: Q <- (I + E) Q = Q + E Q,
+// the product E Q in the working precision T (MFMA, product mode PMODE) and
+// the accumulation in FP64 (Q: FP64 values in the T register layout).
+template <class G, typename T, int PMODE>
+__device__ __forceinline__ void chain_acc(Tile<double>& Q, const Tile<T>& E, const Lane& L, double* s0,
+                                          double* s1) {
+    Tile<T> Qt;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Qt.re[r] = (T)Q.re[r];
+        Qt.im[r] = (T)Q.im[r];
+    }
+    team_sync<G>();
+    slot_store<G, T>(s0, E, L);
+    slot_store<G, T>(s1, Qt, L);
+    team_sync<G>();
+    const Tile<T> P = mulT<G, T, PMODE>(s0, s1, L);
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Q.re[r] += (double)P.re[r];
+        Q.im[r] += (double)P.im[r];
+    }
 }
 
 template <class G, typename T>

@@ -100,6 +100,16 @@ struct DeviceGuard {
     }
 };
 
+// Why the last pm_create / pm_batch_create on this thread failed (no
+// handle exists to carry the message).
+thread_local std::string g_create_err;
+
+pm_status create_fail(pm_status s, const std::string& what, hipError_t e = hipSuccess) {
+    g_create_err = e == hipSuccess ? what : what + ": " + hipGetErrorString(e);
+    (void)hipGetLastError();
+    return s;
+}
+
 double unit_roundoff(int precision) {
     switch (precision) {
         case PM_FP64: return std::ldexp(1.0, -53);
@@ -110,12 +120,15 @@ double unit_roundoff(int precision) {
     }
 }
 
-// Largest theta with theta^(m+1)/(m+1)! / (1 - theta/(m+2)) <= u.
-double taylor_theta(int m, double u) {
-    auto bound = [m](double th) {
+// Largest theta with theta^(m+1)/(m+1)! / (1 - theta/(m+2)) <= u, or, with
+// `relative`, the same bound divided by theta (the remainder relative to
+// ||X|| = theta) <= u.  Both bounds increase on [0, m+2).
+double taylor_theta(int m, double u, bool relative) {
+    auto bound = [m, relative](double th) {
         double t = 1.0;
         for (int k = 1; k <= m + 1; ++k) t *= th / k;
-        return t / (1.0 - th / (m + 2));
+        t /= (1.0 - th / (m + 2));
+        return relative ? (th > 0.0 ? t / th : 0.0) : t;
     };
     double lo = 0.0, hi = m + 1.0;   // bound is increasing on [0, m+2)
     for (int it = 0; it < 200; ++it) {
@@ -165,10 +178,15 @@ double truncation_target(int precision, int64_t n) {
     return std::max(std::ldexp(1.0, -53), u / std::sqrt((double)std::max<int64_t>(n, 1)));
 }
 
+// Reduced-precision modes carry each slice as I + E and accumulate the
+// chains as Q + E Q, so their rounding error scales with ||E|| ~ ||G||; the
+// truncation criterion is relative to ||G|| to match.
+bool relative_truncation(int precision) { return precision != PM_FP64; }
+
 void fill_theta(double* theta, int precision, int64_t n) {
     const double u = truncation_target(precision, n);
     theta[0] = 0.0;
-    for (int m = 1; m <= pm::kMaxDeg; ++m) theta[m] = taylor_theta(m, u);
+    for (int m = 1; m <= pm::kMaxDeg; ++m) theta[m] = taylor_theta(m, u, relative_truncation(precision));
 }
 
 using Mat = std::vector<cplx>;
@@ -516,7 +534,7 @@ const char* pm_status_string(pm_status s) {
     return "PM_E_UNKNOWN";
 }
 
-const char* pm_last_error(const pm_ctx* ctx) { return ctx ? ctx->err.c_str() : ""; }
+const char* pm_last_error(const pm_ctx* ctx) { return ctx ? ctx->err.c_str() : g_create_err.c_str(); }
 
 int64_t pm_basis_count(int64_t n_ctrl, int order) {
     if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl) return -1;
@@ -528,7 +546,7 @@ int64_t pm_basis_count(int64_t n_ctrl, int order) {
 pm_status pm_taylor_theta(int m, int precision, int64_t n_slices, double* theta_out) {
     if (m < 1 || m > PM_MAX_TAYLOR_DEGREE || !theta_out || n_slices < 1) return PM_E_INVALID_ARG;
     if (unit_roundoff(precision) < 0) return PM_E_INVALID_ARG;
-    *theta_out = taylor_theta(m, truncation_target(precision, n_slices));
+    *theta_out = taylor_theta(m, truncation_target(precision, n_slices), relative_truncation(precision));
     return PM_OK;
 }
 
@@ -593,12 +611,11 @@ pm_status pm_slice_weights_host(int64_t n_ctrl, const double* samples, int64_t n
 pm_status pm_create(pm_ctx** out, int device, int precision) {
     if (!out) return PM_E_INVALID_ARG;
     *out = nullptr;
-    if (unit_roundoff(precision) < 0) return PM_E_INVALID_ARG;
+    g_create_err.clear();
+    if (unit_roundoff(precision) < 0) return create_fail(PM_E_INVALID_ARG, "unknown precision");
     int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
-        (void)hipGetLastError();
-        return PM_E_DEVICE;
-    }
+    const hipError_t de = hipGetDeviceCount(&n);
+    if (de != hipSuccess || n <= 0) return create_fail(PM_E_DEVICE, "no HIP device", de);
     if (device < 0 || device >= n) return PM_E_INVALID_ARG;
     pm_ctx* ctx = new (std::nothrow) pm_ctx();
     if (!ctx) return PM_E_OOM;
@@ -962,12 +979,11 @@ extern "C" {
 pm_status pm_batch_create(pm_batch** out, int device, int precision) {
     if (!out) return PM_E_INVALID_ARG;
     *out = nullptr;
-    if (unit_roundoff(precision) < 0) return PM_E_INVALID_ARG;
+    g_create_err.clear();
+    if (unit_roundoff(precision) < 0) return create_fail(PM_E_INVALID_ARG, "unknown precision");
     int n = 0;
-    if (hipGetDeviceCount(&n) != hipSuccess || n <= 0) {
-        (void)hipGetLastError();
-        return PM_E_DEVICE;
-    }
+    const hipError_t de = hipGetDeviceCount(&n);
+    if (de != hipSuccess || n <= 0) return create_fail(PM_E_DEVICE, "no HIP device", de);
     if (device < 0 || device >= n) return PM_E_INVALID_ARG;
     pm_batch* b = new (std::nothrow) pm_batch();
     if (!b) return PM_E_OOM;
@@ -978,9 +994,15 @@ pm_status pm_batch_create(pm_batch** out, int device, int precision) {
     if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) != hipSuccess || cus <= 0)
         cus = 256;
     b->blocks = cus;
-    if (pm::batch_setup(precision) != hipSuccess || hipStreamCreate(&b->cap) != hipSuccess) {
+    const hipError_t se = pm::batch_setup(precision);
+    if (se != hipSuccess) {
         delete b;
-        return PM_E_DEVICE;
+        return create_fail(PM_E_DEVICE, "batch kernel setup (dynamic LDS attribute)", se);
+    }
+    const hipError_t ce = hipStreamCreate(&b->cap);
+    if (ce != hipSuccess) {
+        delete b;
+        return create_fail(PM_E_DEVICE, "capture stream", ce);
     }
     *out = b;
     return PM_OK;
@@ -1192,7 +1214,7 @@ int64_t pm_batch_packets(const pm_batch* b) { return b ? (int64_t)b->packets.siz
 
 int64_t pm_batch_output_doubles(const pm_batch* b) { return b ? b->out_doubles : -1; }
 
-const char* pm_batch_last_error(const pm_batch* b) { return b ? b->err.c_str() : ""; }
+const char* pm_batch_last_error(const pm_batch* b) { return b ? b->err.c_str() : g_create_err.c_str(); }
 
 pm_status pm_tuning_set(const char* key, int dim_class, int precision, int64_t value) {
     if (!key || value < 0 || precision < 0 || precision > 3) return PM_E_INVALID_ARG;

@@ -218,3 +218,25 @@ def test_launch_shape_reports_decomposition(pm):
         assert (c, n) == (7, 143) and l == 36
         U = ctx.equiprop(w.samples, w.h)
     assert orc.relative_frobenius(U, orc.propagate(w.H0, w.Hk, w.samples, w.h, w.order)) <= TOL64
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+@pytest.mark.parametrize("case", ["large_trace", "near_degenerate"])
+def test_small_dims_shift_and_degenerate_spectra(pm, d, case):
+    """Dims <= 4 exponentiate G - (tr G / D) I in the algebra of its powers
+    and restore the phase: a large trace (phase far from 1 per slice) and a
+    nearly scalar H (clustered eigenvalues) must both stay at FP64 parity,
+    in U(T) and in every slice."""
+    w = synth.random_system(d, 2, n_slices=301, h=0.05, order=4, tag=11)
+    H0 = w.H0 + 37.0 * np.eye(d) if case == "large_trace" else 3.0 * np.eye(d) + 1e-9 * w.H0
+    Hk = w.Hk if case == "large_trace" else 1e-9 * w.Hk
+    with pm.Context(0, pm.PM_FP64) as ctx:
+        ctx.set_hamiltonian(H0, Hk, 4)
+        U, sl = ctx.equiprop(w.samples, w.h, return_slices=True)
+    Uo, slo = orc.propagate(H0, Hk, w.samples, w.h, 4, return_slices=True)
+    assert orc.relative_frobenius(U, Uo) <= TOL64
+    assert np.max(np.abs(sl - slo)) <= 1e-13
+    with pm.Context(0, pm.PM_FP32) as ctx:
+        ctx.set_hamiltonian(H0, Hk, 4)
+        U32 = ctx.equiprop(w.samples, w.h)
+    assert orc.relative_frobenius(U32, Uo) <= tol32(301, d) * 4

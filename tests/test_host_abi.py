@@ -100,24 +100,27 @@ def _taylor(X, m):
                                       (pm.PM_BF16_SPLIT, 2.0 ** -16, 1), (pm.PM_FP32, 2.0 ** -32, 2 ** 16),
                                       (pm.PM_FP64, 2.0 ** -53, 2 ** 16)])
 def test_taylor_theta_bounds_truncation(prec, u, n):
-    """theta_m makes the remainder bound equal the truncation target
-    max(2^-53, u/sqrt(N)), and the true truncation error of exp(X) - T_m(X) at
-    ||X||_1 = theta_m (X skew-Hermitian) stays below it."""
+    """FP64: theta_m makes the remainder bound equal 2^-53.  Reduced modes:
+    the bound relative to theta equals u/sqrt(N).  The true truncation error
+    of exp(X) - T_m(X) at ||X||_1 = theta_m (X skew-Hermitian) stays below
+    the bound."""
     rng = np.random.default_rng(4)
     prev = 0.0
+    relative = prec != pm.PM_FP64
     for m in range(1, 22):
         th = pm.taylor_theta(m, prec, n)
         assert th > prev
         prev = th
         bound = th ** (m + 1) / math.factorial(m + 1) / (1 - th / (m + 2))
-        assert abs(bound - u) < 1e-6 * u
+        target = u * th if relative else u
+        assert abs(bound - target) < 1e-6 * target
         if 3 <= m <= 15:
             A = rng.standard_normal((6, 6)) + 1j * rng.standard_normal((6, 6))
             G = 0.5 * (A + A.conj().T)
             G *= th / np.max(np.sum(np.abs(G), axis=0))
             X = -1j * G
             err = np.linalg.norm(scipy.linalg.expm(X) - _taylor(X, m), 1)
-            assert err <= 1.5 * u + 64 * 2.0 ** -53
+            assert err <= 1.5 * target + 64 * 2.0 ** -53
 
 
 def _cost(m):
@@ -153,7 +156,12 @@ def test_create_without_device_reports_device_error():
         pm._lib.pm_destroy(h)
     else:
         assert pm.STATUS[st] == "PM_E_DEVICE"
+        assert "no HIP device" in pm._lib.pm_last_error(None).decode()
+        st = pm._lib.pm_batch_create(ctypes.byref(h), 0, pm.PM_FP32)
+        assert pm.STATUS[st] == "PM_E_DEVICE"
+        assert "no HIP device" in pm._lib.pm_batch_last_error(None).decode()
     assert pm.STATUS[pm._lib.pm_create(ctypes.byref(h), 0, 7)] == "PM_E_INVALID_ARG"
+    assert "precision" in pm._lib.pm_last_error(None).decode()
 
 
 def test_tuning_set_validation(tmp_path):
