@@ -1,0 +1,8 @@
+// VALU engine instantiation: float, dimension 2.
+#include "valu_kernel.h"
+
+namespace pm {
+hipError_t launch_valu_f32_2(const PropParams& p, hipStream_t stream) {
+    return launch_valu_one<float, 2>(p, stream);
+}
+}  // namespace pm

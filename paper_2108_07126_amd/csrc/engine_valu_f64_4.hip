@@ -1,0 +1,8 @@
+// VALU engine instantiation: double, dimension 4.
+#include "valu_kernel.h"
+
+namespace pm {
+hipError_t launch_valu_f64_4(const PropParams& p, hipStream_t stream) {
+    return launch_valu_one<double, 4>(p, stream);
+}
+}  // namespace pm

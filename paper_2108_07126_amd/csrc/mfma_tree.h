@@ -27,21 +27,31 @@ __device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, c
         if (carry && p.store_nodes && active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
         if (!carry) {
             if (active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
-            __threadfence();
+            // publish the node with one agent-scope release before the
+            // ticket, and acquire only as the second arriver of a pair:
+            // these fences write back / invalidate the XCD's L2, so each is
+            // issued once per team where it is needed
             unsigned t;
             if constexpr (G::TW == 1) {
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
                 unsigned v = 0;
                 if (L.lane == 0) v = atomicAdd(&p.counters[poff + par], 1u);
                 t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(v, 0));
+                if (t == 0) return;
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
             } else {
-                __syncthreads();
-                if (active && L.wt == 0 && L.lane == 0) *tick = (int)atomicAdd(&p.counters[poff + par], 1u);
+                __syncthreads();   // every wave's tile of the node is stored
+                if (active && L.wt == 0 && L.lane == 0) {
+                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                    const unsigned v = atomicAdd(&p.counters[poff + par], 1u);
+                    if (v != 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    *tick = (int)v;
+                }
                 __syncthreads();
                 t = (unsigned)*tick;
                 __syncthreads();
+                if (t == 0) return;
             }
-            if (t == 0) return;
-            __threadfence();
             if (active && L.lane == 0 && L.wt == 0) atomicExch(&p.counters[poff + par], 0u);
             const Tile<double> other = active ? node_load<G>(p.nodes + (off + (idx ^ 1)) * NN, L) : Q;
             team_sync<G>();

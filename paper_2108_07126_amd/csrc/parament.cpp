@@ -361,12 +361,21 @@ int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision) {
     return ((c + u - 1) / u) * u;
 }
 
+// Chain length of a propagation: the user's, else the automatic one; whole
+// units, and for the VALU engine at most 2^20 slices (its per-slice output
+// addresses a chain's slices with 32-bit offsets).
+int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N) {
+    int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N, ctx->precision);
+    c = ((c + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
+    if (e.kind == pm::ENGINE_VALU && c > (int64_t(1) << 20)) c = int64_t(1) << 20;
+    return c;
+}
+
 // Workspace and kernel parameters of one propagation on engine e.
 pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, const double* basis, const double* d_samples,
                   int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out) {
     const int64_t N = n_slices_of(ctx->order, n_samples);
-    int64_t chunk = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N, ctx->precision);
-    chunk = ((chunk + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
+    const int64_t chunk = effective_chunk(ctx, e, N);
     const int64_t chains = (N + chunk - 1) / chunk;
     const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
     const size_t node_bytes = (size_t)e.D * e.D * 16;
@@ -467,8 +476,8 @@ bool pick_engine(int du, int precision, EngineInfo* out) {
     if (du <= 4) {
         e.kind = ENGINE_VALU;
         e.D = du <= 2 ? 2 : 4;
-        e.chunk_unit = 64;          // one slice run per lane
-        e.chains_per_leaf = 1;      // a wave is a leaf
+        e.chunk_unit = 256;         // a run of a multiple of 4 slices per lane (two staging groups)
+        e.chains_per_leaf = 4;      // a block of four waves is a leaf
         e.resident_chains = 256 * 8;
     } else {
         e.kind = ENGINE_MFMA;
@@ -669,8 +678,7 @@ pm_status pm_launch_shape(pm_ctx* ctx, int64_t n_samples, int64_t* chunk, int64_
     if (ctx->dim == 0) return fail(ctx, PM_E_NOT_READY, "pm_set_hamiltonian has not been called");
     const int64_t N = n_slices_of(ctx->order, n_samples);
     if (N < 1) return fail(ctx, PM_E_INVALID_ARG, "bad n_samples for the integrator order");
-    int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(ctx->eng, N, ctx->precision);
-    c = ((c + ctx->eng.chunk_unit - 1) / ctx->eng.chunk_unit) * ctx->eng.chunk_unit;
+    const int64_t c = effective_chunk(ctx, ctx->eng, N);
     *chunk = c;
     *chains = (N + c - 1) / c;
     *leaves = (*chains + ctx->eng.chains_per_leaf - 1) / ctx->eng.chains_per_leaf;
