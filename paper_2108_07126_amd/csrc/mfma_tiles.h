@@ -176,9 +176,10 @@ __device__ __forceinline__ Tile<double> relayout_rows(const Tile<double>& t, dou
     }
 }
 
-// Tile (TI, TJ) of A * B, A and B complex D x D in LDS slots.
+// Tile (TI, TJ) of A * B, A and B complex D x D in LDS slots: four real
+// products (the FP32 mode's complex product).
 template <class G, typename T>
-__device__ __forceinline__ Tile<T> slot_mul(const double* A, const double* B, const Lane& L) {
+__device__ __forceinline__ Tile<T> slot_mul4(const double* A, const double* B, const Lane& L) {
     using V = typename V4<T>::type;
     const T* Are = reinterpret_cast<const T*>(A);
     const T* Aim = Are + G::PLANE;
@@ -209,32 +210,43 @@ __device__ __forceinline__ Tile<T> slot_mul(const double* A, const double* B, co
 }
 
 // Complex product as three real products (3M): T1 = Ar Br, T2 = Ai Bi,
-// T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2.  FP32 MFMA.
-template <class G>
-__device__ __forceinline__ Tile<float> slot_mul_3m(const double* A, const double* B, const Lane& L) {
-    const float* Are = reinterpret_cast<const float*>(A);
-    const float* Aim = Are + G::PLANE;
-    const float* Bre = reinterpret_cast<const float*>(B);
-    const float* Bim = Bre + G::PLANE;
-    f4_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+// T3 = (Ar + Ai)(Br + Bi); Re = T1 - T2, Im = T3 - T1 - T2.  FP64 products
+// always take this form (three MFMA chains instead of four; the imaginary
+// part's rounding bound doubles, which FP64 absorbs), FP32 ones in the 3M
+// mode.
+template <class G, typename T>
+__device__ __forceinline__ Tile<T> slot_mul_3m(const double* A, const double* B, const Lane& L) {
+    using V = typename V4<T>::type;
+    const T* Are = reinterpret_cast<const T*>(A);
+    const T* Aim = Are + G::PLANE;
+    const T* Bre = reinterpret_cast<const T*>(B);
+    const T* Bim = Bre + G::PLANE;
+    V t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
     const int arow = (16 * L.TI + L.j) * G::LD;
     const int bcol = 16 * L.TJ + L.j;
 #pragma unroll
     for (int kb = 0; kb < G::D / 4; ++kb) {
         const int k = 4 * kb + L.g;
-        const float ar = Are[arow + k], ai = Aim[arow + k];
-        const float br = Bre[k * G::LD + bcol], bi = Bim[k * G::LD + bcol];
+        const T ar = Are[arow + k], ai = Aim[arow + k];
+        const T br = Bre[k * G::LD + bcol], bi = Bim[k * G::LD + bcol];
         t1 = mfma16(ar, br, t1);
         t2 = mfma16(ai, bi, t2);
         t3 = mfma16(ar + ai, br + bi, t3);
     }
-    Tile<float> out;
+    Tile<T> out;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         out.re[r] = t1[r] - t2[r];
         out.im[r] = t3[r] - t1[r] - t2[r];
     }
     return out;
+}
+
+// The engines' complex product: 3M in FP64, four real products in FP32.
+template <class G, typename T>
+__device__ __forceinline__ Tile<T> slot_mul(const double* A, const double* B, const Lane& L) {
+    if constexpr (std::is_same<T, double>::value) return slot_mul_3m<G, double>(A, B, L);
+    else return slot_mul4<G, T>(A, B, L);
 }
 
 typedef short s4_t __attribute__((ext_vector_type(4)));
@@ -313,7 +325,7 @@ __device__ __forceinline__ Tile<T> mulT(const double* A, const double* B, const 
     if constexpr (std::is_same<T, double>::value || PMODE == 0) {
         return slot_mul<G, T>(A, B, L);
     } else if constexpr (PMODE == 1) {
-        return slot_mul_3m<G>(A, B, L);
+        return slot_mul_3m<G, float>(A, B, L);
     } else {
         return slot_mul_bf16s<G>(A, B, L);
     }
