@@ -73,6 +73,13 @@ SIGNATURES = {
 
 
 def _load():
+    # PyTorch (device memory and streams for the *_dev entry points) ships its
+    # own HIP runtime; loading it first makes the library bind to that same
+    # runtime, so one process never holds two
+    try:
+        import torch  # noqa: F401
+    except ImportError:
+        pass
     if not os.path.exists(LIB_PATH):
         raise ImportError(
             f"{LIB_PATH} is missing: build the HIP library first "
