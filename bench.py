@@ -13,6 +13,8 @@ the launch stream), the oracle's CPU rate, and one object per leg:
   slices       the headline workload with every U_j written to HBM
   d64          the dim-64 precision sweep (2^16 slices), every mode, MFMA roofline
   small        dims 2, 4 and 8 with per-slice output (HBM roofline)
+  chebyshev    the paper's Chebyshev-series exponential (FP64) on the headline
+               and dim-64 workloads, beside the Taylor series
   grad         fidelity-gradient evals/s on the 3-qubit register
   batch        512 uneven instances in one graph-captured launch
   cpu          the oracle's rate and every mode's error against it
@@ -48,7 +50,7 @@ TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_tiles.h", "mfma_tree.h", "engine_com
 MEASURED_TRAFFIC = {"bytes": (2.0 * 4433.9375 + 1.0 * 4139.90625) * 1024.0,
                     "sources_sha256": "a3f44b7cf4ad98502eef67344c865ed86f89328369d947f21f69c0b1d2e96896",
                     "profile": "profiles/propagate_d16_random_qudit_traffic.md"}
-LEGS = ["precisions", "slices", "d64", "small", "grad", "batch", "cpu", "fixed_error"]
+LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "grad", "batch", "cpu", "fixed_error"]
 
 
 def taylor_products(m: int) -> int:
@@ -202,6 +204,30 @@ def leg_small(pm, torch, dev, args, out):
     out["small"] = res
 
 
+def leg_chebyshev(pm, torch, dev, args, out):
+    """FP64 propagation with the Chebyshev series (Clenshaw, Table-1
+    degrees) on the headline and dim-64 workloads."""
+    import synth
+    res = {}
+    for label, w in (("random_qudit_d16_N2^17", synth.random_qudit()),
+                     ("precision_sweep_d64_N2^16", synth.precision_sweep())):
+        s_dev = torch.from_numpy(w.samples).to(dev)
+        U = torch.zeros((w.dim, w.dim), dtype=torch.complex128, device=dev)
+        row = {}
+        for name, method in (("taylor", pm.PM_EXPM_TAYLOR), ("chebyshev", pm.PM_EXPM_CHEBYSHEV)):
+            ctx = pm.Context(0, pm.PM_FP64)
+            ctx.set_hamiltonian(w.H0, w.Hk, w.order)
+            ctx.set_expm_method(method)
+            steps = max(3, args.steps // (4 if w.dim == 64 else 1))
+            _, k = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U), steps, 2)
+            row[name] = {"kernel_ms": k, "steps_per_s": w.n_slices / (k * 1e-3)}
+            row[name + "_U"] = U.cpu().numpy()
+            ctx.close()
+        row["chebyshev_over_taylor_time"] = row["chebyshev"]["kernel_ms"] / row["taylor"]["kernel_ms"]
+        res[label] = row
+    out["chebyshev"] = res
+
+
 def leg_copy(torch, dev, out):
     """A plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB): the
     calibration kernel for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -314,6 +340,8 @@ def main():
         leg_small(pm, torch, dev, args, out)
     if "copy" in legs:
         leg_copy(torch, dev, out)
+    if "chebyshev" in legs:
+        leg_chebyshev(pm, torch, dev, args, out)
 
     wg = None
     if "grad" in legs:
@@ -356,6 +384,9 @@ def main():
         out["cpu_baseline"] = {"value": N / dt_cpu, "unit": "steps/s", "cores": blas_threads(), "kind": "oracle",
                                "sample": f"the whole workload ({N} slices, one run, {dt_cpu:.1f} s)"}
         out["error_vs_oracle"] = {name: orc.relative_frobenius(Ug[name], Uo) for name, _ in modes}
+        if "chebyshev" in out:
+            row = out["chebyshev"]["random_qudit_d16_N2^17"]
+            out["error_vs_oracle"]["fp64_chebyshev"] = orc.relative_frobenius(row["chebyshev_U"], Uo)
         if wg is not None:
             _, go = orc.control_gradient(wg.H0, wg.Hk, wg.samples, wg.h, 2,
                                          orc.fidelity_grad_U(orc.propagate(wg.H0, wg.Hk, wg.samples, wg.h, 2),
@@ -398,6 +429,10 @@ def main():
         res["summary"] = summ
         out["fixed_error"] = res
 
+    if "chebyshev" in out:
+        for row in out["chebyshev"].values():
+            row.pop("taylor_U", None)
+            row.pop("chebyshev_U", None)
     print(json.dumps(out), flush=True)
 
 

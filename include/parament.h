@@ -75,6 +75,15 @@ typedef enum pm_precision {
 #define PM_MAX_DIM 64
 /* Largest Taylor degree the planner may choose. */
 #define PM_MAX_TAYLOR_DEGREE 21
+/* Largest Chebyshev degree (Table 1 of the paper ends at 25). */
+#define PM_MAX_CHEBYSHEV_DEGREE 25
+
+/* How the slice exponentials are evaluated (Matrix exponential section). */
+typedef enum pm_expm_method {
+    PM_EXPM_TAYLOR = 0,    /* truncated Taylor series with scaling and squaring (default) */
+    PM_EXPM_CHEBYSHEV = 1  /* the paper's Chebyshev series (eq. chebychev_series), Clenshaw
+                              recurrence (Algorithm 1), with scaling and squaring */
+} pm_expm_method;
 
 /* Create a context on HIP device `device` computing in `precision`.
  * *out receives the handle (NULL on failure).  Allocates nothing on the
@@ -212,6 +221,17 @@ pm_status pm_tuning_set(const char *key, int dim_class, int precision, int64_t v
 pm_status pm_set_expm_policy(pm_ctx *ctx, int max_taylor_degree, int force_s);
 pm_status pm_set_chunk(pm_ctx *ctx, int64_t chunk);
 
+/* Choose the exponential (pm_expm_method) for pm_equiprop / pm_equiprop_dev.
+ * PM_EXPM_CHEBYSHEV: per slice, with nu = ||G_j||_1 (the spectrum lies in
+ * [-nu, nu]), the planner picks the degree m <= PM_MAX_CHEBYSHEV_DEGREE and
+ * squarings s minimising m + s (Clenshaw takes m products) with
+ * nu / 2^s <= theta_m, theta_m from pm_chebyshev_theta; the series is taken
+ * on the interval [-theta_m, theta_m] (it contains the scaled spectrum), so
+ * its coefficients a_k = (-i)^k J_k(theta_m) depend on m only.  Dimensions
+ * <= 4 first shift G by tr G / D.  PM_FP64 contexts only (PM_E_UNSUPPORTED
+ * otherwise); the gradient entry points always use the Taylor series. */
+pm_status pm_set_expm_method(pm_ctx *ctx, int method);
+
 /* The decomposition a propagation of n_samples samples would use on this
  * context (after pm_set_hamiltonian; host-only, nothing is launched):
  * *chunk slices per chain, *chains chains, *leaves leaves of the pairwise
@@ -274,6 +294,18 @@ pm_status pm_taylor_theta(int m, int precision, int64_t n_slices, double *theta_
  * n_slices slices: Taylor degree m and squarings s minimising the product
  * count (ties to the smaller s), subject to nu / 2^s <= theta_m and
  * m <= max_degree. */
+/* Table 1 of the paper: the largest ||G|| for which the degree-m Chebyshev
+ * series meets Lubich's estimate (eq. error_chebychev)
+ *     4 (exp(1 - rho^2) rho)^(m+1) <= u,   rho = 2 ||G|| / (4m + 4),
+ * with u = 2^-53 (PM_FP64), 2^-24 (FP32 modes) or 2^-16 (BF16 split).
+ * 1 <= m <= PM_MAX_CHEBYSHEV_DEGREE. */
+pm_status pm_chebyshev_theta(int m, int precision, double *theta_out);
+
+/* The Chebyshev planner's (m, s) for ||G||_1 = nu (see pm_set_expm_method);
+ * force_s >= 0 fixes s and takes the smallest feasible degree. */
+pm_status pm_plan_chebyshev(double nu, int precision, int max_degree, int force_s, int *m_out,
+                            int *s_out);
+
 pm_status pm_plan_expm(double nu, int precision, int max_degree, int64_t n_slices,
                        int *m_out, int *s_out);
 

@@ -21,6 +21,8 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libparament.so")
 
 PM_FP64, PM_FP32, PM_FP32_3M, PM_BF16_SPLIT = 0, 1, 2, 3
+PM_EXPM_TAYLOR, PM_EXPM_CHEBYSHEV = 0, 1
+MAX_CHEBYSHEV_DEGREE = 25
 PRECISIONS = {"fp64": PM_FP64, "fp32": PM_FP32, "fp32_3m": PM_FP32_3M, "bf16_split": PM_BF16_SPLIT}
 STATUS = ["PM_OK", "PM_E_INVALID_ARG", "PM_E_NOT_READY", "PM_E_NOT_HERMITIAN", "PM_E_OOM",
           "PM_E_DEVICE", "PM_E_UNSUPPORTED"]
@@ -57,6 +59,10 @@ SIGNATURES = {
     "pm_tuning_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64]),
     "pm_set_expm_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "pm_set_chunk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "pm_set_expm_method": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
+    "pm_chebyshev_theta": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_double_p]),
+    "pm_plan_chebyshev": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
+                                         _c_int_p]),
     "pm_launch_shape": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64, ctypes.POINTER(ctypes.c_int64),
                                        ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)]),
     "pm_status_string": (ctypes.c_char_p, [ctypes.c_int]),
@@ -179,6 +185,20 @@ def plan_expm(nu: float, precision: int = PM_FP64, max_degree: int = MAX_TAYLOR_
     return m.value, s.value
 
 
+def chebyshev_theta(m: int, precision: int = PM_FP64) -> float:
+    """Table-1 limit of the degree-m Chebyshev series (Lubich's estimate)."""
+    t = ctypes.c_double()
+    _check(_lib.pm_chebyshev_theta(m, precision, ctypes.byref(t)))
+    return t.value
+
+
+def plan_chebyshev(nu: float, precision: int = PM_FP64, max_degree: int = MAX_CHEBYSHEV_DEGREE,
+                   force_s: int = -1) -> Tuple[int, int]:
+    m, s = ctypes.c_int(), ctypes.c_int()
+    _check(_lib.pm_plan_chebyshev(nu, precision, max_degree, force_s, ctypes.byref(m), ctypes.byref(s)))
+    return m.value, s.value
+
+
 def n_slices(n_samples: int, order: int) -> int:
     return n_samples if order == 2 else (n_samples - 1) // 2
 
@@ -235,6 +255,10 @@ class Context:
 
     def set_chunk(self, chunk: int = 0):
         _check(_lib.pm_set_chunk(self._h, chunk), self._h)
+
+    def set_expm_method(self, method: int = PM_EXPM_TAYLOR):
+        """PM_EXPM_TAYLOR (default) or PM_EXPM_CHEBYSHEV (the paper's series)."""
+        _check(_lib.pm_set_expm_method(self._h, method), self._h)
 
     def launch_shape(self, n_samples: int) -> Tuple[int, int, int]:
         """(chunk, chains, leaves) a propagation of n_samples would use."""

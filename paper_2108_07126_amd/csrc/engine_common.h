@@ -159,6 +159,34 @@ __device__ __forceinline__ void plan_expm_lanes(const PropParams& p, double nu, 
     s_out = (key >> 5) & 63;
 }
 
+// Chebyshev planner (Clenshaw takes m products): lane l tests degree l + 1
+// against its interval half-width (preloaded in lane_ctheta, +inf past the
+// last degree); minimise m + s, ties to the smaller s.  With force_s >= 0
+// the smallest feasible degree (the largest if none is).
+__device__ __forceinline__ double lane_ctheta_of(const PropParams& p, int lane) {
+    return lane < kMaxCheb ? p.ctheta[lane + 1] : __builtin_inf();
+}
+
+__device__ __forceinline__ void plan_cheb_lanes(const PropParams& p, double nu, int lane, double lane_ctheta,
+                                                int& m_out, int& s_out) {
+    // the candidates occupy lanes 0..24: minimum over the first two rows
+    auto min2rows = [](int k) {
+        const int r = row16_min_i(k);
+        return min(__builtin_amdgcn_readlane(r, 0), __builtin_amdgcn_readlane(r, 16));
+    };
+    const bool cand = lane_ctheta < __builtin_inf();
+    if (p.force_s >= 0) {
+        const int key = min2rows((cand && ldexp(nu, -p.force_s) <= lane_ctheta) ? lane : 1 << 20);
+        m_out = key < kMaxCheb ? key + 1 : kMaxCheb;
+        s_out = p.force_s;
+        return;
+    }
+    const int s = min(min_squarings(nu, cand ? lane_ctheta : 1.0), 63);
+    const int key = min2rows(cand ? ((lane + 1 + s) << 12) | (s << 6) | lane : 0x7fffffff);
+    m_out = (key & 63) + 1;
+    s_out = (key >> 6) & 63;
+}
+
 // Branch-free form of slice_weight for a lane-dependent basis index m: the
 // lane gathers up to five samples of the slice and combines them with the
 // formula of its basis matrix.  Lanes m >= M get weight 0.

@@ -76,6 +76,7 @@ propagate_mfma(PropParams p) {
     // slice's samples are loaded while this slice is exponentiated
     const WeightRecipe wr = weight_recipe(p, L.lane);
     const double lth = lane_theta_of(p, L.lane);
+    const double lcth = lane_ctheta_of(p, L.lane);
     SliceSamples smp = gather_samples(p, wr, j0 < j1 ? j0 : 0);
     for (int64_t j = j0; j < j1; ++j) {
         const double wl = combine_weight(p, wr, smp);
@@ -96,7 +97,9 @@ propagate_mfma(PropParams p) {
         // plan (FP64)
         const double nu = wave_uniform(team_norm1<G, T>(gre, gim, L, red));
         int m, s;
-        plan_expm_lanes(p, nu, L.lane, lth, m, s);
+        const bool cheb = kF64 && p.method == PM_EXPM_CHEBYSHEV;
+        if (cheb) plan_cheb_lanes(p, nu, L.lane, lcth, m, s);
+        else plan_expm_lanes(p, nu, L.lane, lth, m, s);
         m = wave_uniform(m);
         s = wave_uniform(s);
         Tile<T> Gt;
@@ -107,7 +110,8 @@ propagate_mfma(PropParams p) {
         }
         if constexpr (kF64) {
             // exponentiate, square, store, chain product Q <- U Q
-            Tile<T> U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
+            Tile<T> U = cheb ? cheb_exp<G>(Gt, m, p.ctheta[m], p.cheb_j + m * (kMaxCheb + 1), L, s0, s1)
+                             : taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
             if (s > 0) U = square_n<G, double>(U, s, L, s0);
             if (p.slices_out) store_slice<G, T>(p, j, U, L);
             team_sync<G>();

@@ -424,6 +424,61 @@ __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s
     return U;
 }
 
+// exp(-i G) for a (pre-scaled) Hermitian tile set by the degree-m Chebyshev
+// series on the interval [-theta, theta] that holds its spectrum
+// (eq. chebychev_series with alpha = -theta, beta = theta, so the phase
+// factor is 1): X = G / theta, a_k = (-i)^k J_k(theta) (row `jk` of the
+// coefficient table), and the Clenshaw recurrence of Algorithm 1,
+// D_k = a_k I + 2 X D_{k+1} - D_{k+2}, result D_0 - D_2.  m products.  FP64.
+template <class G>
+__device__ Tile<double> cheb_exp(const Tile<double>& Gt, int m, double theta, const double* jk, const Lane& L,
+                                 double* s0, double* s1) {
+    const double inv = 1.0 / theta;
+    Tile<double> X, D1, D2, keep;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        X.re[r] = Gt.re[r] * inv;
+        X.im[r] = Gt.im[r] * inv;
+        D1.re[r] = D1.im[r] = D2.re[r] = D2.im[r] = keep.re[r] = keep.im[r] = 0.0;
+    }
+    team_sync<G>();
+    slot_store<G, double>(s0, X, L);   // X stays in s0
+    for (int k = m; k >= 0; --k) {
+        Tile<double> P;
+        if (k < m) {
+            team_sync<G>();
+            slot_store<G, double>(s1, D1, L);
+            team_sync<G>();
+            P = slot_mul<G, double>(s0, s1, L);
+        } else {
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P.re[r] = P.im[r] = 0.0;
+        }
+        // a_k = (-i)^k J_k: real for even k (sign + - + -), imaginary for odd
+        const double jv = jk[k];
+        const int q = k & 3;
+        const double are = q == 0 ? jv : (q == 2 ? -jv : 0.0);
+        const double aim = q == 1 ? -jv : (q == 3 ? jv : 0.0);
+        Tile<double> Dk;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool diag = 16 * L.TI + crow<double>(L.g, r) == 16 * L.TJ + L.j;
+            Dk.re[r] = fma(2.0, P.re[r], -D2.re[r]) + (diag ? are : 0.0);
+            Dk.im[r] = fma(2.0, P.im[r], -D2.im[r]) + (diag ? aim : 0.0);
+        }
+        if (k == 0) keep = D2;
+        D2 = D1;
+        D1 = Dk;
+    }
+    Tile<double> U;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        U.re[r] = D1.re[r] - keep.re[r];
+        U.im[r] = D1.im[r] - keep.im[r];
+    }
+    return U;
+}
+
 template <class G, typename T>
 __device__ __forceinline__ Tile<T> square_n(Tile<T> U, int s, const Lane& L, double* s0) {
     for (int i = 0; i < s; ++i) {

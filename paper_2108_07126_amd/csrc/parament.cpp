@@ -45,6 +45,8 @@ struct pm_ctx {
     int max_degree = PM_MAX_TAYLOR_DEGREE;
     int force_s = -1;
     int64_t chunk_override = 0;
+    int method = PM_EXPM_TAYLOR;
+    double* d_cheb = nullptr;    // Chebyshev coefficient table on the device
     // device buffers
     double* d_basis = nullptr;
     double* d_nodes = nullptr;
@@ -187,6 +189,47 @@ void fill_theta(double* theta, int precision, int64_t n) {
     const double u = truncation_target(precision, n);
     theta[0] = 0.0;
     for (int m = 1; m <= pm::kMaxDeg; ++m) theta[m] = taylor_theta(m, u, relative_truncation(precision));
+}
+
+// Lubich's estimate of the Chebyshev truncation error (eq. error_chebychev)
+// for degree m and spectral width w = beta - alpha.
+double lubich_error(int m, double w) {
+    const double rho = w / (4.0 * m + 4.0);
+    return 4.0 * std::pow(std::exp(1.0 - rho * rho) * rho, m + 1);
+}
+
+// Largest ||G|| with lubich_error(m, 2 ||G||) <= u; the estimate increases in
+// rho up to rho = 1/sqrt(2), which brackets the root.
+double chebyshev_theta(int m, double u) {
+    double lo = 0.0, hi = 1.0 / std::sqrt(2.0);
+    for (int it = 0; it < 200; ++it) {
+        const double mid = 0.5 * (lo + hi);
+        if (lubich_error(m, mid * (4.0 * m + 4.0)) <= u) lo = mid; else hi = mid;
+    }
+    return lo * (4.0 * m + 4.0) / 2.0;
+}
+
+void plan_chebyshev_host(const double* ctheta, int md, int force_s, double nu, int* m_out, int* s_out) {
+    if (force_s >= 0) {
+        const double x = std::ldexp(nu, -force_s);
+        int m = md;
+        for (int c = 1; c <= md; ++c)
+            if (ctheta[c] >= x) { m = c; break; }
+        *m_out = m;
+        *s_out = force_s;
+        return;
+    }
+    int bm = md, bs = 0, bc = 1 << 30;
+    for (int s = 0; s < 64 && s < bc; ++s) {
+        const double x = std::ldexp(nu, -s);
+        for (int c = 1; c <= md; ++c)
+            if (ctheta[c] >= x) {
+                if (c + s < bc) { bc = c + s; bm = c; bs = s; }
+                break;
+            }
+    }
+    *m_out = bm;
+    *s_out = bs;
 }
 
 using Mat = std::vector<cplx>;
@@ -411,6 +454,13 @@ pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, const double* basis, con
     p.du = (int)ctx->dim;
     p.max_degree = ctx->max_degree;
     p.force_s = ctx->force_s;
+    p.method = ctx->method;
+    p.cheb_j = ctx->d_cheb;
+    if (ctx->method == PM_EXPM_CHEBYSHEV) {
+        const double u = unit_roundoff(ctx->precision);
+        p.ctheta[0] = 0.0;
+        for (int m = 1; m <= pm::kMaxCheb; ++m) p.ctheta[m] = chebyshev_theta(m, u);
+    }
     // D = 16: the block keeps the basis in LDS when it is small (<= 64 KiB)
     p.basis_lds = (e.kind == pm::ENGINE_MFMA && e.D == 16 &&
                    (size_t)ctx->M * e.D * e.D * 16 <= 64 * 1024) ? 1 : 0;
@@ -440,6 +490,7 @@ pm_status launch_grad(pm_ctx* ctx, const double* d_samples, int64_t n_samples, d
     pm_status st = ensure(ctx, (void**)&ctx->d_UT, &ctx->ut_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "U(T)");
     if (st != PM_OK) return st;
     st = prepare(ctx, e, basis, d_samples, n_samples, dt, ctx->d_UT, nullptr, &p);
+    p.method = PM_EXPM_TAYLOR;   // the adjoint differentiates the Taylor evaluation
     if (st != PM_OK) return st;
     st = ensure(ctx, (void**)&ctx->d_chain, &ctx->chain_bytes, (size_t)p.n_chains * e.D * e.D * 16,
                 "chain products");
@@ -559,6 +610,24 @@ pm_status pm_taylor_theta(int m, int precision, int64_t n_slices, double* theta_
     return PM_OK;
 }
 
+pm_status pm_chebyshev_theta(int m, int precision, double* theta_out) {
+    if (m < 1 || m > PM_MAX_CHEBYSHEV_DEGREE || !theta_out || unit_roundoff(precision) < 0)
+        return PM_E_INVALID_ARG;
+    *theta_out = chebyshev_theta(m, unit_roundoff(precision));
+    return PM_OK;
+}
+
+pm_status pm_plan_chebyshev(double nu, int precision, int max_degree, int force_s, int* m_out, int* s_out) {
+    if (!m_out || !s_out || !(nu >= 0.0) || max_degree < 1 || max_degree > PM_MAX_CHEBYSHEV_DEGREE ||
+        force_s < -1 || force_s > 62 || unit_roundoff(precision) < 0)
+        return PM_E_INVALID_ARG;
+    double ct[pm::kMaxCheb + 1];
+    ct[0] = 0.0;
+    for (int m = 1; m <= pm::kMaxCheb; ++m) ct[m] = chebyshev_theta(m, unit_roundoff(precision));
+    plan_chebyshev_host(ct, max_degree, force_s, nu, m_out, s_out);
+    return PM_OK;
+}
+
 pm_status pm_plan_expm(double nu, int precision, int max_degree, int64_t n_slices, int* m_out,
                        int* s_out) {
     if (!m_out || !s_out || !(nu >= 0.0) || max_degree < 1 || max_degree > PM_MAX_TAYLOR_DEGREE ||
@@ -645,6 +714,7 @@ pm_status pm_destroy(pm_ctx* ctx) {
         dfree(ctx->d_samples);
         dfree(ctx->d_U);
         dfree(ctx->d_basis_grad);
+        dfree(ctx->d_cheb);
         dfree(ctx->d_chain);
         dfree(ctx->d_gw);
         dfree(ctx->d_UT);
@@ -669,6 +739,36 @@ pm_status pm_set_expm_policy(pm_ctx* ctx, int max_taylor_degree, int force_s) {
 pm_status pm_set_chunk(pm_ctx* ctx, int64_t chunk) {
     if (!ctx || chunk < 0) return ctx ? fail(ctx, PM_E_INVALID_ARG, "chunk must be >= 0") : PM_E_INVALID_ARG;
     ctx->chunk_override = chunk;
+    return PM_OK;
+}
+
+pm_status pm_set_expm_method(pm_ctx* ctx, int method) {
+    if (!ctx) return PM_E_INVALID_ARG;
+    if (method != PM_EXPM_TAYLOR && method != PM_EXPM_CHEBYSHEV)
+        return fail(ctx, PM_E_INVALID_ARG, "unknown expm method");
+    if (method == PM_EXPM_CHEBYSHEV && ctx->precision != PM_FP64)
+        return fail(ctx, PM_E_UNSUPPORTED, "the Chebyshev series is built for PM_FP64 contexts only");
+    if (method == PM_EXPM_CHEBYSHEV && !ctx->d_cheb) {
+        // coefficient table J_k(theta_m), k <= m, for every degree m
+        const double u = unit_roundoff(ctx->precision);
+        std::vector<double> tab((size_t)(pm::kMaxCheb + 1) * (pm::kMaxCheb + 1), 0.0);
+        for (int m = 1; m <= pm::kMaxCheb; ++m) {
+            const double th = chebyshev_theta(m, u);
+            for (int k = 0; k <= m; ++k)
+                tab[(size_t)m * (pm::kMaxCheb + 1) + k] = std::cyl_bessel_j((double)k, th);
+        }
+        DeviceGuard g(ctx->device);
+        void* ptr = nullptr;
+        hipError_t e = hipMalloc(&ptr, tab.size() * sizeof(double));
+        if (e != hipSuccess) return hip_fail(ctx, e, "Chebyshev table");
+        e = hipMemcpy(ptr, tab.data(), tab.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (e != hipSuccess) {
+            (void)hipFree(ptr);
+            return hip_fail(ctx, e, "Chebyshev table upload");
+        }
+        ctx->d_cheb = static_cast<double*>(ptr);
+    }
+    ctx->method = method;
     return PM_OK;
 }
 

@@ -12,6 +12,7 @@ namespace pm {
 constexpr int kMaxCtrl = 8;
 constexpr int kMaxBasis = 1 + 2 * kMaxCtrl + kMaxCtrl * (kMaxCtrl - 1) / 2;  // 45
 constexpr int kMaxDeg = PM_MAX_TAYLOR_DEGREE;
+constexpr int kMaxCheb = PM_MAX_CHEBYSHEV_DEGREE;
 
 // Everything one propagation launch needs, passed by value as the kernel
 // argument.  Pointers are device pointers.
@@ -34,6 +35,9 @@ struct PropParams {
     int K, M, order, du;
     int max_degree, force_s;
     int basis_lds;               // MFMA engine: block keeps a copy of the basis in LDS
+    int method;                  // PM_EXPM_TAYLOR or PM_EXPM_CHEBYSHEV
+    const double* cheb_j;        // Chebyshev: [m][k] = J_k(ctheta[m]), k <= m <= kMaxCheb
+    double ctheta[kMaxCheb + 1]; // Chebyshev: half-width of the spectral interval for degree m
     uint8_t pair_a[kMaxBasis];   // order 4: control indices of i[H_a, H_b]
     uint8_t pair_b[kMaxBasis];
 };

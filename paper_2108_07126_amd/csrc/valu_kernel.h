@@ -232,9 +232,81 @@ __device__ __forceinline__ double herm_trace_prod(const Herm<D, T>& a, const Her
 // truncated series as the matrix evaluation; only the order of operations
 // differs.  With EXCESS the result is exp(-i X) - I (accurate relative to
 // ||X||).
-template <int D, typename T, bool EXCESS>
-__device__ __forceinline__ Mat<D, T> taylor_exp_ch(const Herm<D, T>& x, int m) {
+// Clenshaw recurrence of the Chebyshev series in the algebra:
+// D_k = a_k I + 2 X D_{k+1} - D_{k+2} on complex coefficient vectors,
+// a_k = (-i)^k J_k(theta) from the table row jk; result D_0 - D_2.
+template <int D>
+__device__ __forceinline__ void ch_clenshaw(const double (&r)[D], int m, const double* jk, double (&cre)[D],
+                                            double (&cim)[D]) {
+    double d1r[D], d1i[D], d2r[D], d2i[D], kr[D], ki[D];
+#pragma unroll
+    for (int i = 0; i < D; ++i) d1r[i] = d1i[i] = d2r[i] = d2i[i] = kr[i] = ki[i] = 0.0;
+#pragma unroll
+    for (int k = kMaxCheb; k >= 0; --k) {
+        if (k > m) continue;
+        double pr[D], pi[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            pr[i] = d1r[i];
+            pi[i] = d1i[i];
+        }
+        ch_step<D>(pr, r);
+        ch_step<D>(pi, r);
+        const double jv = jk[k];
+        const int q = k & 3;
+        double dr[D], di[D];
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            dr[i] = fma(2.0, pr[i], -d2r[i]);
+            di[i] = fma(2.0, pi[i], -d2i[i]);
+        }
+        dr[0] += q == 0 ? jv : (q == 2 ? -jv : 0.0);
+        di[0] += q == 1 ? -jv : (q == 3 ? jv : 0.0);
+        if (k == 0) {
+#pragma unroll
+            for (int i = 0; i < D; ++i) {
+                kr[i] = d2r[i];
+                ki[i] = d2i[i];
+            }
+        }
+#pragma unroll
+        for (int i = 0; i < D; ++i) {
+            d2r[i] = d1r[i];
+            d2i[i] = d1i[i];
+            d1r[i] = dr[i];
+            d1i[i] = di[i];
+        }
+    }
+#pragma unroll
+    for (int i = 0; i < D; ++i) {
+        cre[i] = d1r[i] - kr[i];
+        cim[i] = d1i[i] - ki[i];
+    }
+}
+
+enum { EXP_TAYLOR = 0, EXP_TAYLOR_EXCESS = 1, EXP_CHEBYSHEV = 2 };
+
+// exp(-i X) of a pre-scaled Hermitian X, evaluated in the algebra generated
+// by X: by Cayley-Hamilton every power X^k with k >= D is a combination of
+// I, X, .., X^{D-1}, so the polynomial is carried as D complex coefficients
+// (scalar recurrences) and the matrix is formed once from the powers
+// X^0..X^{D-1}.  KIND: the degree-m Taylor series (EXP_TAYLOR), the same
+// without its identity term (EXP_TAYLOR_EXCESS: exp(-i X) - I, accurate
+// relative to ||X||), or the degree-m Chebyshev series on [-theta, theta]
+// (EXP_CHEBYSHEV; X is first divided by theta).  The results are the same
+// truncated series as the matrix evaluations; only the order of operations
+// differs.
+template <int D, typename T, int KIND>
+__device__ __forceinline__ Mat<D, T> exp_ch(Herm<D, T> x, int m, const double* jk = nullptr, double theta = 1.0) {
     static_assert(D == 2 || D == 4, "algebra evaluation for D = 2 and 4");
+    if constexpr (KIND == EXP_CHEBYSHEV) {
+        const T inv = (T)(1.0 / theta);
+#pragma unroll
+        for (int e = 0; e < Herm<D, T>::NE; ++e) {
+            x.re[e] *= inv;
+            x.im[e] *= inv;
+        }
+    }
     double pw[D + 1];
     double tr1 = 0.0;
 #pragma unroll
@@ -251,7 +323,8 @@ __device__ __forceinline__ Mat<D, T> taylor_exp_ch(const Herm<D, T>& x, int m) {
     }
     double r[D], cre[D], cim[D];
     ch_coeffs<D>(pw, r);
-    ch_taylor<D, EXCESS>(r, m, cre, cim);
+    if constexpr (KIND == EXP_CHEBYSHEV) ch_clenshaw<D>(r, m, jk, cre, cim);
+    else ch_taylor<D, KIND == EXP_TAYLOR_EXCESS>(r, m, cre, cim);
     // U = sum_i c_i X^i; (X^i)_{ba} = conj((X^i)_{ab})
     Mat<D, T> U;
 #pragma unroll
@@ -597,7 +670,9 @@ propagate_valu(PropParams p) {
     const int64_t run = wave < p.n_chains ? p.chunk / 64 : 0;
     const int64_t base = wave * p.chunk + (int64_t)lane * run;
     const double lth = lane_theta_of(p, lane);
+    const double lcth = lane_ctheta_of(p, lane);
     constexpr bool kF64 = std::is_same<T, double>::value;
+    const bool cheb = kF64 && p.method == PM_EXPM_CHEBYSHEV;
     // The scalar phases e^{-i mu_j} commute with everything: the chain
     // multiplies the phase-free factors and the lane applies e^{-i sum mu}
     // once at the end of its run.  FP64: Q <- U Q.  Reduced modes: slices as
@@ -622,7 +697,8 @@ propagate_valu(PropParams p) {
         for (int a = 0; a < D; ++a) g.re[hidx<D>(a, a)] -= mu;
         const double nu = (double)wave_max_f(norm1_bound<D>(g));
         int m, s;
-        plan_valu(p, nu, lane, lth, m, s);
+        if (cheb) plan_cheb_lanes(p, nu, lane, lcth, m, s);
+        else plan_valu(p, nu, lane, lth, m, s);
         Herm<D, T> x;
 #pragma unroll
         for (int e = 0; e < Herm<D, T>::NE; ++e) {
@@ -630,14 +706,15 @@ propagate_valu(PropParams p) {
             x.im[e] = (T)ldexp(g.im[e], -s);
         }
         if constexpr (kF64) {
-            Mat<D, T> U = taylor_exp_ch<D, T, false>(x, m);
+            Mat<D, T> U = cheb ? exp_ch<D, T, EXP_CHEBYSHEV>(x, m, p.cheb_j + m * (kMaxCheb + 1), p.ctheta[m])
+                               : exp_ch<D, T, EXP_TAYLOR>(x, m);
             for (int k = 0; k < s; ++k) U = mat_mul(U, U);
             if constexpr (OUT == OUT_STAGED) stage_phased<D, T>(srow + r * S::SB, U, mu, false);
             if constexpr (OUT == OUT_DIRECT)
                 if (valid) store_phased<D, T>(p, j, U, mu, false);
             mat_lmul_inplace<D, T>(U, Q);
         } else {
-            Mat<D, T> E = taylor_exp_ch<D, T, true>(x, m);
+            Mat<D, T> E = exp_ch<D, T, EXP_TAYLOR_EXCESS>(x, m);
             if (s > 0) {
                 // (I + E)^2 - I = 2E + E E, in FP64
                 Mat<D, double> Ed = mat_convert<D, double>(E);

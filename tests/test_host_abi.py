@@ -179,3 +179,35 @@ def test_tuning_set_validation(tmp_path):
     t.write_text("# comment\nchains 16 0 0\nbatch_chunk 64 2 0  # default\nchains 7 0 5\nbad line\n")
     assert pm.load_tuning(str(t)) == 2
     pm.load_tuning()  # restore the shipped table, if any
+
+
+def test_chebyshev_thresholds_reproduce_table1():
+    """The library's Chebyshev limits (its own solver of Lubich's estimate)
+    against the values printed in the paper's Table 1."""
+    import os
+    path = os.path.join(os.path.dirname(__file__), "golden", "chebyshev_table1.txt")
+    rows = [l.split("#", 1)[0].split() for l in open(path)]
+    rows = [r for r in rows if r]
+    assert len(rows) == 12
+    for m, f32, f64 in rows:
+        for printed, prec in ((f32, pm.PM_FP32), (f64, pm.PM_FP64)):
+            mant = printed.split("e")[0]
+            dec = len(mant.split(".")[1]) if "." in mant else 0
+            scale = 10.0 ** (int(printed.split("e")[1]) - dec) if "e" in printed else 10.0 ** (-dec)
+            assert abs(pm.chebyshev_theta(int(m), prec) - float(printed)) <= 0.5 * scale + 1e-12, (m, printed)
+
+
+@pytest.mark.parametrize("prec", [pm.PM_FP64, pm.PM_FP32])
+def test_chebyshev_planner_is_feasible_and_optimal(prec):
+    th = {m: pm.chebyshev_theta(m, prec) for m in range(1, 26)}
+    for nu in [0.0, 1e-9, 3e-4, 0.0043, 0.0346, 0.195, 0.43, 1.0, 3.7, 40.0, 1e4]:
+        m, s = pm.plan_chebyshev(nu, prec)
+        assert nu / 2 ** s <= th[m]
+        best = min(mm + ss for ss in range(0, 40) for mm in th if nu / 2 ** ss <= th[mm])
+        assert m + s == best
+        # ties go to the smaller s
+        assert s == min(ss for ss in range(0, 40) for mm in th if nu / 2 ** ss <= th[mm] and mm + ss == best)
+    m, s = pm.plan_chebyshev(0.3, prec, force_s=3)
+    assert s == 3 and m == min(mm for mm in th if 0.3 / 8 <= th[mm])
+    with pytest.raises(pm.ParamentError):
+        pm.plan_chebyshev(1.0, prec, max_degree=26)
