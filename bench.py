@@ -15,6 +15,7 @@ the launch stream), the oracle's CPU rate, and one object per leg:
   small        dims 2, 4 and 8 with per-slice output (HBM roofline)
   chebyshev    the paper's Chebyshev-series exponential (FP64) on the headline
                and dim-64 workloads, beside the Taylor series
+  trajectory   every partial product U(t_j) of the headline workload (FP64)
   grad         fidelity-gradient evals/s on the 3-qubit register
   batch        512 uneven instances in one graph-captured launch
   cpu          the oracle's rate and every mode's error against it
@@ -50,7 +51,8 @@ TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_tiles.h", "mfma_tree.h", "engine_com
 MEASURED_TRAFFIC = {"bytes": (2.0 * 4433.9375 + 1.0 * 4139.90625) * 1024.0,
                     "sources_sha256": "a3f44b7cf4ad98502eef67344c865ed86f89328369d947f21f69c0b1d2e96896",
                     "profile": "profiles/propagate_d16_random_qudit_traffic.md"}
-LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "grad", "batch", "cpu", "fixed_error"]
+LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "trajectory", "grad", "batch", "cpu",
+        "fixed_error"]
 
 
 def taylor_products(m: int) -> int:
@@ -228,6 +230,21 @@ def leg_chebyshev(pm, torch, dev, args, out):
     out["chebyshev"] = res
 
 
+def leg_trajectory(pm, torch, dev, args, out):
+    """All N+1 partial products of the headline workload (4 KiB each)."""
+    import synth
+    w = synth.random_qudit()
+    s_dev = torch.from_numpy(w.samples).to(dev)
+    ctx = pm.Context(0, pm.PM_FP64)
+    ctx.set_hamiltonian(w.H0, w.Hk, w.order)
+    P = torch.empty((w.n_slices + 1, 16, 16), dtype=torch.complex128, device=dev)
+    wall, k = time_launches(lambda: ctx.trajectory_dev(s_dev, w.h, P), max(3, args.steps // 2), 2)
+    out["trajectory"] = {"workload": "random_qudit_d16_N2^17, propagators", "ms": k,
+                         "steps_per_s": w.n_slices / (k * 1e-3), "out_bytes": P.numel() * 16,
+                         "out_gbs": P.numel() * 16 / (k * 1e-3) / 1e9}
+    ctx.close()
+
+
 def leg_copy(torch, dev, out):
     """A plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB): the
     calibration kernel for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -342,6 +359,8 @@ def main():
         leg_copy(torch, dev, out)
     if "chebyshev" in legs:
         leg_chebyshev(pm, torch, dev, args, out)
+    if "trajectory" in legs:
+        leg_trajectory(pm, torch, dev, args, out)
 
     wg = None
     if "grad" in legs:

@@ -140,6 +140,28 @@ pm_status pm_backward_dev(pm_ctx *ctx, const double *samples_dev, int64_t n_samp
                           double dt, const double *W_dev, double *grad_dev,
                           double *U_out_dev, void *stream);
 
+/* What a trajectory holds at every slice boundary t_j = j h, j = 0..N
+ * (P_j = U_{j-1} ... U_0, P_0 = I): */
+typedef enum pm_trajectory_kind {
+    PM_TRAJ_PROPAGATORS = 0,  /* P_j                        out [N+1][dim][dim]   */
+    PM_TRAJ_STATES = 1,       /* P_j Psi_0, Psi_0 [dim][n]  out [N+1][dim][n]     */
+    PM_TRAJ_DENSITY = 2       /* P_j rho_0 P_j^H            out [N+1][dim][dim]   */
+} pm_trajectory_kind;
+
+/* Time evolution at every slice boundary (the trajectory of eq. slices'
+ * partial products; states psi(t) = U(t) psi_0 and rho(t) = U(t) rho_0
+ * U(t)^H, Computational approach section).  A forward pass keeps the
+ * product tree (as the gradient does); each chain then starts from its
+ * checkpoint product and multiplies its recomputed slices in, writing the
+ * prefix before each slice.  x0_dev: NULL for PM_TRAJ_PROPAGATORS, device
+ * complex128 [dim][n_vec] states (1 <= n_vec <= dim) for PM_TRAJ_STATES,
+ * device complex128 [dim][dim] for PM_TRAJ_DENSITY.  out_dev: device
+ * complex128, N+1 blocks as listed above.  Enqueued on `stream`; PM_FP64
+ * contexts only (PM_E_UNSUPPORTED otherwise); Taylor series. */
+pm_status pm_trajectory_dev(pm_ctx *ctx, const double *samples_dev, int64_t n_samples, double dt,
+                            int kind, const double *x0_dev, int64_t n_vec, double *out_dev,
+                            void *stream);
+
 /* Gate-fidelity loss and its gradient with host buffers (synchronous):
  * L = 1 - |Tr(V^H U(T))|^2 / dim^2 for the target V (host complex128
  * [dim][dim]); *loss receives L, grad (host float64 [n_ctrl][n_samples])

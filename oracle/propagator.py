@@ -47,6 +47,7 @@ __all__ = [
     "expm_minus_i",
     "ordered_product",
     "propagate",
+    "trajectory",
     "unitarity_defect",
     "fidelity_loss",
     "fidelity_grad_U",
@@ -123,6 +124,23 @@ def propagate(H0, Hk, samples, h: float, order: int, return_slices: bool = False
             slices[s:e] = Uj
         U = ordered_product(Uj, U)
     return (U, slices) if return_slices else U
+
+
+def trajectory(H0, Hk, samples, h: float, order: int) -> np.ndarray:
+    """Every partial product P_j = U_{j-1} ... U_0, j = 0..N (P_0 = I,
+    P_N = U(T)), taken sequentially: the time evolution at each slice
+    boundary t_j = j h (eq. slices read at intermediate times)."""
+    samples = np.asarray(samples, dtype=np.float64)
+    n = samples.shape[1] if order == 2 else (samples.shape[1] - 1) // 2
+    d = np.asarray(H0).shape[0]
+    out = np.empty((n + 1, d, d), dtype=np.complex128)
+    out[0] = np.eye(d)
+    for s in range(0, n, _CHUNK):
+        e = min(n, s + _CHUNK)
+        Uj = expm_minus_i(slice_exponents(H0, Hk, samples, h, order, s, e))
+        for q in range(e - s):
+            out[s + q + 1] = Uj[q] @ out[s + q]
+    return out
 
 
 def unitarity_defect(U: np.ndarray) -> float:

@@ -22,6 +22,7 @@ LIB_PATH = os.path.join(_HERE, "libparament.so")
 
 PM_FP64, PM_FP32, PM_FP32_3M, PM_BF16_SPLIT = 0, 1, 2, 3
 PM_EXPM_TAYLOR, PM_EXPM_CHEBYSHEV = 0, 1
+PM_TRAJ_PROPAGATORS, PM_TRAJ_STATES, PM_TRAJ_DENSITY = 0, 1, 2
 MAX_CHEBYSHEV_DEGREE = 25
 PRECISIONS = {"fp64": PM_FP64, "fp32": PM_FP32, "fp32_3m": PM_FP32_3M, "bf16_split": PM_BF16_SPLIT}
 STATUS = ["PM_OK", "PM_E_INVALID_ARG", "PM_E_NOT_READY", "PM_E_NOT_HERMITIAN", "PM_E_OOM",
@@ -44,6 +45,9 @@ SIGNATURES = {
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pm_backward_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_trajectory_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                         ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
+                                         ctypes.c_void_p]),
     "pm_fidelity_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                         ctypes.c_void_p, _c_double_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pm_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int]),
@@ -216,6 +220,7 @@ class Context:
         if st != 0:
             raise ParamentError(st, "pm_create: " + _lib.pm_last_error(None).decode())
         self._h = h
+        self.device = device
         self.precision = precision
         self.dim = None
         self.n_ctrl = None
@@ -299,6 +304,48 @@ class Context:
                                     ctypes.c_void_p(slices_t.data_ptr()) if slices_t is not None else None,
                                     ctypes.c_void_p(stream.cuda_stream)), self._h)
 
+
+    def trajectory_dev(self, samples_t, dt: float, out_t, kind: int = PM_TRAJ_PROPAGATORS, x0_t=None,
+                       stream=None):
+        """Time evolution at every slice boundary into out_t (device
+        complex128 [N+1][d][d], or [N+1][d][n] for states); x0_t: device
+        complex128 states [d][n] or density [d][d]."""
+        import torch
+        assert samples_t.is_cuda and samples_t.dtype == torch.float64 and samples_t.is_contiguous()
+        assert out_t.is_cuda and out_t.dtype == torch.complex128 and out_t.is_contiguous()
+        n_vec = 0
+        if x0_t is not None:
+            assert x0_t.is_cuda and x0_t.dtype == torch.complex128 and x0_t.is_contiguous()
+            n_vec = x0_t.shape[1] if x0_t.dim() == 2 else 1
+        if stream is None:
+            stream = torch.cuda.current_stream(out_t.device)
+        S = samples_t.shape[-1]
+        _check(_lib.pm_trajectory_dev(self._h, ctypes.c_void_p(samples_t.data_ptr()), S, float(dt), kind,
+                                      ctypes.c_void_p(x0_t.data_ptr()) if x0_t is not None else None, n_vec,
+                                      ctypes.c_void_p(out_t.data_ptr()), ctypes.c_void_p(stream.cuda_stream)),
+               self._h)
+
+    def trajectory(self, samples, dt: float, kind: int = PM_TRAJ_PROPAGATORS, x0=None) -> np.ndarray:
+        """Host convenience over trajectory_dev (device buffers from torch)."""
+        import torch
+        s = np.ascontiguousarray(np.asarray(samples, np.float64))
+        if s.ndim == 1:
+            s = s[None]
+        d = self.dim
+        N = n_slices(s.shape[1], self.order)
+        dev = torch.device("cuda", self.device)
+        st = torch.from_numpy(s).to(dev)
+        x0_t = None
+        cols = d
+        if kind == PM_TRAJ_STATES:
+            x0 = _as_c128(x0).reshape(d, -1)
+            cols = x0.shape[1]
+        if x0 is not None and kind != PM_TRAJ_PROPAGATORS:
+            x0_t = torch.from_numpy(_as_c128(x0).reshape(d, cols)).to(dev)
+        out = torch.empty((N + 1, d, cols), dtype=torch.complex128, device=dev)
+        self.trajectory_dev(st, dt, out, kind, x0_t)
+        torch.cuda.synchronize(dev)
+        return out.cpu().numpy()
 
     def fidelity_grad(self, samples, dt: float, V):
         """Gate-fidelity loss 1 - |Tr(V^H U)|^2/d^2, its gradient w.r.t. the

@@ -221,6 +221,34 @@ __device__ __forceinline__ double team_sum(double x, const Lane& L, double* red)
     }
 }
 
+// The product of every slice before `chain` (U_{j0-1} ... U_0) from a forward
+// pass that kept its tree nodes and chain products: the aligned
+// power-of-two node ranges over the blocks before this one (earliest range
+// first), then this block's earlier chains.
+template <class G>
+__device__ Tile<double> chain_checkpoint(const PropParams& p, int64_t chain, const Lane& L, double* s0,
+                                         double* s1) {
+    const int64_t NN = (int64_t)G::D * G::D * 2;
+    Tile<double> P = ident<double>(L);
+    const int64_t b = chain / G::NT;
+    int nlev = 0;
+    for (int64_t cnt = p.n_leaves; cnt > 1; cnt = (cnt + 1) >> 1) ++nlev;
+    for (int l = nlev; l >= 0; --l) {
+        if ((b >> l) & 1) {
+            int64_t off = 0, cnt = p.n_leaves;
+            for (int q = 0; q < l; ++q) {
+                off += cnt;
+                cnt = (cnt + 1) >> 1;
+            }
+            const Tile<double> nd = node_load<G>(p.nodes + (off + (b >> l) - 1) * NN, L);
+            P = mul2<G>(nd, P, L, s0, s1);
+        }
+    }
+    for (int64_t c = b * G::NT; c < chain; ++c)
+        P = mul2<G>(node_load<G>(p.chain_out + c * NN, L), P, L, s0, s1);
+    return P;
+}
+
 template <int D, int NT, bool BL>
 __global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
 __attribute__((amdgpu_waves_per_eu(D == 64 ? 4 : 2, 8)))
@@ -253,29 +281,9 @@ backward_mfma(GradParams gp) {
     if (chain >= p.n_chains) return;   // no block-wide barrier follows
     const int64_t j0 = chain * p.chunk;
     const int64_t j1 = min(p.n_slices, j0 + p.chunk);
-    const int64_t NN = (int64_t)D * D * 2;
 
-    // checkpoint P = U_{j0-1} ... U_0: aligned tree nodes over the blocks
-    // before this one (earliest range first), then this block's earlier chains
-    Tile<double> P = ident<double>(L);
-    {
-        const int64_t b = blockIdx.x;
-        int nlev = 0;
-        for (int64_t cnt = p.n_leaves; cnt > 1; cnt = (cnt + 1) >> 1) ++nlev;
-        for (int l = nlev; l >= 0; --l) {
-            if ((b >> l) & 1) {
-                int64_t off = 0, cnt = p.n_leaves;
-                for (int q = 0; q < l; ++q) {
-                    off += cnt;
-                    cnt = (cnt + 1) >> 1;
-                }
-                const Tile<double> nd = node_load<G>(p.nodes + (off + (b >> l) - 1) * NN, L);
-                P = mul2<G>(nd, P, L, s0, s1);
-            }
-        }
-        for (int64_t c = b * NT; c < chain; ++c)
-            P = mul2<G>(node_load<G>(p.chain_out + c * NN, L), P, L, s0, s1);
-    }
+    // checkpoint P = U_{j0-1} ... U_0
+    const Tile<double> P = chain_checkpoint<G>(p, chain, L, s0, s1);
     // Omega_{j0} = P Z P^H, Z = W^H U(T)
     const Tile<double> Wt = load_user<G>(gp.W, p.du, 0.0, L);
     const Tile<double> UTt = load_user<G>(gp.UT, p.du, 1.0, L);
@@ -340,6 +348,122 @@ backward_mfma(GradParams gp) {
     }
 }
 
+// Rows < rows and columns < cols of a tile set from a row-major complex
+// block with leading dimension ld (zero elsewhere).
+template <class G>
+__device__ __forceinline__ Tile<double> load_block(const double* A, int rows, int cols, int ld, const Lane& L) {
+    Tile<double> t;
+    const int col = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        const bool in = row < rows && col < cols;
+        t.re[r] = in ? A[(row * ld + col) * 2 + 0] : 0.0;
+        t.im[r] = in ? A[(row * ld + col) * 2 + 1] : 0.0;
+    }
+    return t;
+}
+
+template <class G>
+__device__ __forceinline__ void store_block(double* A, const Tile<double>& t, int rows, int cols, int ld,
+                                            const Lane& L) {
+    const int col = 16 * L.TJ + L.j;
+    if (col >= cols) return;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        if (row < rows) {
+            A[(row * ld + col) * 2 + 0] = t.re[r];
+            A[(row * ld + col) * 2 + 1] = t.im[r];
+        }
+    }
+}
+
+// Trajectory: every prefix P_j = U_{j-1} ... U_0, j = 0..N (applied to a
+// block of states, or to a density matrix), from the same checkpoints as the
+// gradient: each chain starts from its checkpoint and multiplies its
+// recomputed slices in, writing its rows of the output before each slice;
+// the last chain also writes j = N.
+template <int D, int NT, bool BL>
+__global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
+__attribute__((amdgpu_waves_per_eu(D == 64 ? 4 : 2, 8)))
+trajectory_mfma(TrajParams tp) {
+    using G = Geo<D, NT>;
+    const PropParams& p = tp.p;
+    extern __shared__ double dsm[];
+    double* slots = dsm;
+    double* red = slots + NT * 2 * G::SLOT;
+    double* lbasis = red + G::TD * D + 2;
+
+    Lane L;
+    L.lane = threadIdx.x & 63;
+    L.g = L.lane >> 4;
+    L.j = L.lane & 15;
+    const int wave = wave_uniform((int)(threadIdx.x >> 6));
+    const int team = wave / G::TW;
+    L.wt = wave % G::TW;
+    L.TI = L.wt / G::TD;
+    L.TJ = L.wt % G::TD;
+    double* s0 = slots + team * 2 * G::SLOT;
+    double* s1 = s0 + G::SLOT;
+    if constexpr (BL) {
+        const int n = p.M * G::TW * 512;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
+        __syncthreads();
+    }
+    const double* bas = BL ? lbasis : p.basis;
+    const int64_t chain = (int64_t)blockIdx.x * NT + team;
+    if (chain >= p.n_chains) return;   // no block-wide barrier follows
+    const int64_t j0 = chain * p.chunk;
+    const int64_t j1 = min(p.n_slices, j0 + p.chunk);
+    const int du = p.du;
+    const int cols = tp.kind == PM_TRAJ_STATES ? tp.n_vec : du;
+    const int64_t stride = (int64_t)du * cols * 2;
+
+    // S_j: P_j, P_j Psi_0 or P_j rho_0 P_j^H at the chain's first slice
+    Tile<double> S = chain_checkpoint<G>(p, chain, L, s0, s1);
+    if (tp.kind == PM_TRAJ_STATES) {
+        S = mul2<G>(S, load_block<G>(tp.x0, du, cols, cols, L), L, s0, s1);
+    } else if (tp.kind == PM_TRAJ_DENSITY) {
+        S = mul_adjB<G>(mul2<G>(S, load_block<G>(tp.x0, du, du, du, L), L, s0, s1), S, L, s0, s1);
+    }
+    const WeightRecipe wr = weight_recipe(p, L.lane);
+    const double lth = lane_theta_of(p, L.lane);
+    SliceSamples smp = gather_samples(p, wr, j0);
+    const int64_t bofs = mfma_basis_index(D, 0, L.TI, L.TJ, 0, 0, L.lane);
+    for (int64_t j = j0; j < j1; ++j) {
+        store_block<G>(tp.out + j * stride, S, du, cols, cols, L);
+        const double wl = combine_weight(p, wr, smp);
+        if (j + 1 < j1) smp = gather_samples(p, wr, j + 1);
+        double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
+#pragma unroll 4
+        for (int m = 0; m < p.M; ++m) {
+            const double w = readlane_d(wl, m);
+            const double* bb = bas + bofs + (int64_t)m * G::TW * 512;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                gre[r] = fma(w, bb[r * 64], gre[r]);
+                gim[r] = fma(w, bb[256 + r * 64], gim[r]);
+            }
+        }
+        const double nu = wave_uniform(team_norm1<G, double>(gre, gim, L, red));
+        int m, s;
+        plan_expm_lanes(p, nu, L.lane, lth, m, s);
+        m = wave_uniform(m);
+        s = wave_uniform(s);
+        Tile<double> Gt;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Gt.re[r] = ldexp(gre[r], -s);
+            Gt.im[r] = ldexp(gim[r], -s);
+        }
+        const Tile<double> U = square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
+        S = mul2<G>(U, S, L, s0, s1);
+        if (tp.kind == PM_TRAJ_DENSITY) S = mul_adjB<G>(S, U, L, s0, s1);
+    }
+    if (j1 == p.n_slices) store_block<G>(tp.out + p.n_slices * stride, S, du, cols, cols, L);
+}
+
 // dL/d samples from dL/dw by the weight formulas of the expand step; one
 // thread per (control, sample).
 __global__ void __launch_bounds__(256) samples_grad(GradParams gp, double* grad) {
@@ -399,9 +523,38 @@ hipError_t launch_bwd(const GradParams& gp, size_t lds, hipStream_t stream) {
     return hipGetLastError();
 }
 
+template <int D, int NT, bool BL>
+hipError_t launch_traj(const TrajParams& tp, size_t lds, hipStream_t stream) {
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)trajectory_mfma<D, NT, BL>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int64_t blocks = (tp.p.n_chains + NT - 1) / NT;
+    hipLaunchKernelGGL((trajectory_mfma<D, NT, BL>), dim3((unsigned)blocks), dim3(64 * (D / 16) * (D / 16) * NT),
+                       lds, stream, tp);
+    return hipGetLastError();
+}
+
 }  // namespace
 
 int mfma_chains_per_block(int D);
+
+hipError_t launch_trajectory(int D, const TrajParams& tp, hipStream_t stream) {
+    const int NT = mfma_chains_per_block(D);
+    const int TD = D / 16;
+    size_t lds = sizeof(double) * ((size_t)NT * 2 * 2 * D * (D + 1) + (size_t)TD * D + 2);
+    const bool bl = tp.p.basis_lds != 0;
+    if (bl) lds += sizeof(double) * (size_t)tp.p.M * TD * TD * 512;
+    switch (D) {
+        case 16: return bl ? launch_traj<16, 4, true>(tp, lds, stream) : launch_traj<16, 4, false>(tp, lds, stream);
+        case 32: return launch_traj<32, 1, false>(tp, lds, stream);
+        case 64: return launch_traj<64, 1, false>(tp, lds, stream);
+        default: return hipErrorInvalidValue;
+    }
+}
 
 hipError_t launch_backward(int D, const GradParams& gp, double* grad_samples, hipStream_t stream) {
     const int NT = mfma_chains_per_block(D);

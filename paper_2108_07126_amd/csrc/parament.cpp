@@ -481,27 +481,38 @@ pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double
 
 // Gradient: forward on the FP64 MFMA engine keeping chain products and every
 // tree node (U(T) into ctx->d_UT), then the backward kernels.
-pm_status launch_grad(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt,
-                      const double* d_W, double* d_grad, hipStream_t stream, bool run_forward,
-                      bool run_backward) {
+// Forward pass on the FP64 gradient engine that keeps every tree node and
+// chain product (the checkpoints of the gradient and the trajectory).
+pm_status forward_keep(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt, hipStream_t stream,
+                       bool run_forward, pm::PropParams* out) {
     const pm::EngineInfo& e = ctx->geng;
     const double* basis = ctx->d_basis_grad ? ctx->d_basis_grad : ctx->d_basis;
-    pm::PropParams p;
+    pm::PropParams& p = *out;
     pm_status st = ensure(ctx, (void**)&ctx->d_UT, &ctx->ut_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "U(T)");
     if (st != PM_OK) return st;
     st = prepare(ctx, e, basis, d_samples, n_samples, dt, ctx->d_UT, nullptr, &p);
-    p.method = PM_EXPM_TAYLOR;   // the adjoint differentiates the Taylor evaluation
     if (st != PM_OK) return st;
+    p.method = PM_EXPM_TAYLOR;   // the adjoint and the trajectory use the Taylor evaluation
     st = ensure(ctx, (void**)&ctx->d_chain, &ctx->chain_bytes, (size_t)p.n_chains * e.D * e.D * 16,
                 "chain products");
     if (st != PM_OK) return st;
     p.chain_out = ctx->d_chain;
     p.store_nodes = 1;
-    hipError_t he;
     if (run_forward) {
-        he = pm::launch_propagate(e, PM_FP64, p, stream);
+        const hipError_t he = pm::launch_propagate(e, PM_FP64, p, stream);
         if (he != hipSuccess) return hip_fail(ctx, he, "forward launch");
     }
+    return PM_OK;
+}
+
+pm_status launch_grad(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt,
+                      const double* d_W, double* d_grad, hipStream_t stream, bool run_forward,
+                      bool run_backward) {
+    const pm::EngineInfo& e = ctx->geng;
+    pm::PropParams p;
+    pm_status st = forward_keep(ctx, d_samples, n_samples, dt, stream, run_forward, &p);
+    if (st != PM_OK) return st;
+    hipError_t he;
     if (!run_backward) return PM_OK;
     st = ensure(ctx, (void**)&ctx->d_gw, &ctx->gw_bytes, sizeof(double) * (size_t)p.n_slices * p.M,
                 "weight gradients");
@@ -944,6 +955,32 @@ pm_status pm_backward_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samp
                                        hipMemcpyDeviceToDevice, st);
         if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpyAsync U");
     }
+    return PM_OK;
+}
+
+pm_status pm_trajectory_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samples, double dt, int kind,
+                            const double* x0_dev, int64_t n_vec, double* out_dev, void* stream) {
+    pm_status s = check_prop_args(ctx, n_samples, dt);
+    if (s != PM_OK) return s;
+    if (ctx->precision != PM_FP64) return fail(ctx, PM_E_UNSUPPORTED, "trajectories are built for PM_FP64 contexts");
+    if (kind != PM_TRAJ_PROPAGATORS && kind != PM_TRAJ_STATES && kind != PM_TRAJ_DENSITY)
+        return fail(ctx, PM_E_INVALID_ARG, "unknown trajectory kind");
+    if (kind == PM_TRAJ_STATES && (n_vec < 1 || n_vec > ctx->dim))
+        return fail(ctx, PM_E_INVALID_ARG, "n_vec must be in [1, dim]");
+    if (!out_dev || (kind != PM_TRAJ_PROPAGATORS && !x0_dev) || (ctx->n_ctrl > 0 && !samples_dev))
+        return fail(ctx, PM_E_INVALID_ARG, "null pointer");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    pm::TrajParams tp;
+    s = forward_keep(ctx, samples_dev, n_samples, dt, st, true, &tp.p);
+    if (s != PM_OK) return s;
+    tp.kind = kind;
+    tp.x0 = x0_dev;
+    tp.n_vec = kind == PM_TRAJ_STATES ? (int)n_vec : (int)ctx->dim;
+    tp.out = out_dev;
+    const hipError_t he = pm::launch_trajectory(ctx->geng.D, tp, st);
+    if (he != hipSuccess) return hip_fail(ctx, he, "trajectory launch");
     return PM_OK;
 }
 

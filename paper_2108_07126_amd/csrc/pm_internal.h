@@ -50,6 +50,17 @@ struct GradParams {
     double* gw;         // [N][M] dL / d w_{j,m}
 };
 
+// Trajectory kernel arguments (PM_TRAJ_* kinds of the public header).
+struct TrajParams {
+    PropParams p;       // forward parameters; p.nodes and p.chain_out filled by the forward
+    int kind;           // propagators, states or density
+    const double* x0;   // [du][n_vec] states or [du][du] density, complex128; unused for propagators
+    int n_vec;          // state columns
+    double* out;        // [N+1][du][cols] complex128
+};
+
+hipError_t launch_trajectory(int D, const TrajParams& tp, hipStream_t stream);
+
 // Batched instances: a packet is up to teams(D) consecutive chains of one
 // instance, run in lockstep by one block of the persistent batch kernel.
 struct BatchPacket {

@@ -365,3 +365,38 @@ def test_planted_sampling_mistake_is_caught():
         e.append(orc.relative_frobenius(U, circular_drive_exact(1.0, 0.1, 1.0, 6.0)))
     slope = -np.polyfit(np.log(ns), np.log(e), 1)[0]
     assert abs(slope - 2.0) > 0.5
+
+
+def test_trajectory_static_closed_form_and_end_point():
+    """Constant H: every partial product is exp(-i H t_j), from one
+    eigendecomposition at each time; the last one is propagate()'s U(T)."""
+    import synth
+    w = synth.random_system(5, 2, n_slices=40, h=0.03, order=2, tag=21)
+    c = np.repeat(np.array([[0.7], [-0.2]]), 40, axis=1)
+    H = w.H0 + 0.7 * w.Hk[0] - 0.2 * w.Hk[1]
+    P = orc.trajectory(w.H0, w.Hk, c, 0.03, 2)
+    lam, Q = np.linalg.eigh(H)
+    for j in (0, 1, 17, 40):
+        ref = (Q * np.exp(-1j * lam * 0.03 * j)) @ Q.conj().T
+        assert np.max(np.abs(P[j] - ref)) < 1e-13
+    w4 = synth.random_system(4, 2, n_slices=33, h=0.05, order=4, tag=22)
+    P4 = orc.trajectory(w4.H0, w4.Hk, w4.samples, w4.h, 4)
+    assert P4.shape == (34, 4, 4)
+    assert np.max(np.abs(P4[-1] - orc.propagate(w4.H0, w4.Hk, w4.samples, w4.h, 4))) < 1e-13
+    assert np.allclose(P4[0], np.eye(4))
+
+
+def test_trajectory_follows_circular_drive_closed_form():
+    """The driven two-level system's closed-form U(t) (rotating frame) at
+    every slice boundary, to the 4th-order Magnus accuracy."""
+    import synth
+    w = synth.circular_drive(n_slices=400, order=4)
+    P = orc.trajectory(w.H0, w.Hk, w.samples, w.h, 4)
+    w0, w1, wr = w.meta["w0"], w.meta["w1"], w.meta["wrf"]
+    sz = np.diag([1.0, -1.0]).astype(complex)
+    sx = np.array([[0, 1], [1, 0]], dtype=complex)
+    for j in (0, 100, 257, 400):
+        t = j * w.h
+        rot = scipy.linalg.expm(-1j * wr * t * sz / 2)
+        eff = scipy.linalg.expm(-1j * t * (0.5 * (w0 - wr) * sz + 0.5 * w1 * sx))
+        assert np.max(np.abs(P[j] - rot @ eff)) < 1e-8
