@@ -162,6 +162,25 @@ pm_status pm_trajectory_dev(pm_ctx *ctx, const double *samples_dev, int64_t n_sa
                             int kind, const double *x0_dev, int64_t n_vec, double *out_dev,
                             void *stream);
 
+/* Optimisers of pm_grape_dev. */
+typedef enum pm_optimizer {
+    PM_OPT_GD = 0,    /* c <- c - step * grad                                        */
+    PM_OPT_ADAM = 1   /* Adam (beta1 0.9, beta2 0.999, eps 1e-8, bias-corrected moments) */
+} pm_optimizer;
+
+/* Gradient-based optimal control of the gate fidelity (GRAPE, Applications
+ * and outlook section): `iters` updates of the control samples samples_dev
+ * (device float64 [n_ctrl][n_samples], overwritten with the optimised
+ * controls) for L = 1 - |Tr(V^H U(T))|^2 / dim^2, V_dev device complex128
+ * [dim][dim].  Each iteration runs the checkpointed forward pass, the loss
+ * (on the device), the adjoint and the update; loss_dev (device float64,
+ * iters + 1 values) receives L before every update and after the last.  The
+ * whole loop is enqueued on `stream` without host synchronisation.  PM_FP64
+ * contexts only; Taylor series. */
+pm_status pm_grape_dev(pm_ctx *ctx, double *samples_dev, int64_t n_samples, double dt,
+                       const double *V_dev, int iters, double step, int optimizer,
+                       double *loss_dev, void *stream);
+
 /* Gate-fidelity loss and its gradient with host buffers (synchronous):
  * L = 1 - |Tr(V^H U(T))|^2 / dim^2 for the target V (host complex128
  * [dim][dim]); *loss receives L, grad (host float64 [n_ctrl][n_samples])

@@ -23,6 +23,7 @@ LIB_PATH = os.path.join(_HERE, "libparament.so")
 PM_FP64, PM_FP32, PM_FP32_3M, PM_BF16_SPLIT = 0, 1, 2, 3
 PM_EXPM_TAYLOR, PM_EXPM_CHEBYSHEV = 0, 1
 PM_TRAJ_PROPAGATORS, PM_TRAJ_STATES, PM_TRAJ_DENSITY = 0, 1, 2
+PM_OPT_GD, PM_OPT_ADAM = 0, 1
 MAX_CHEBYSHEV_DEGREE = 25
 PRECISIONS = {"fp64": PM_FP64, "fp32": PM_FP32, "fp32_3m": PM_FP32_3M, "bf16_split": PM_BF16_SPLIT}
 STATUS = ["PM_OK", "PM_E_INVALID_ARG", "PM_E_NOT_READY", "PM_E_NOT_HERMITIAN", "PM_E_OOM",
@@ -48,6 +49,9 @@ SIGNATURES = {
     "pm_trajectory_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                          ctypes.c_int, ctypes.c_void_p, ctypes.c_int64, ctypes.c_void_p,
                                          ctypes.c_void_p]),
+    "pm_grape_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                    ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int, ctypes.c_void_p,
+                                    ctypes.c_void_p]),
     "pm_fidelity_grad": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                         ctypes.c_void_p, _c_double_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pm_batch_create": (ctypes.c_int, [ctypes.POINTER(ctypes.c_void_p), ctypes.c_int, ctypes.c_int]),
@@ -346,6 +350,24 @@ class Context:
         self.trajectory_dev(st, dt, out, kind, x0_t)
         torch.cuda.synchronize(dev)
         return out.cpu().numpy()
+
+    def grape_dev(self, samples_t, dt: float, V_t, iters: int, step: float, optimizer: int = PM_OPT_ADAM,
+                  loss_t=None, stream=None):
+        """Optimise the controls in place (device float64 [K][S]) for the gate
+        V_t (device complex128 [d][d]); returns the device loss history
+        (iters + 1 values)."""
+        import torch
+        assert samples_t.is_cuda and samples_t.dtype == torch.float64 and samples_t.is_contiguous()
+        assert V_t.is_cuda and V_t.dtype == torch.complex128 and V_t.is_contiguous()
+        if loss_t is None:
+            loss_t = torch.empty(iters + 1, dtype=torch.float64, device=samples_t.device)
+        if stream is None:
+            stream = torch.cuda.current_stream(samples_t.device)
+        _check(_lib.pm_grape_dev(self._h, ctypes.c_void_p(samples_t.data_ptr()), samples_t.shape[-1], float(dt),
+                                 ctypes.c_void_p(V_t.data_ptr()), int(iters), float(step), int(optimizer),
+                                 ctypes.c_void_p(loss_t.data_ptr()), ctypes.c_void_p(stream.cuda_stream)),
+               self._h)
+        return loss_t
 
     def fidelity_grad(self, samples, dt: float, V):
         """Gate-fidelity loss 1 - |Tr(V^H U)|^2/d^2, its gradient w.r.t. the

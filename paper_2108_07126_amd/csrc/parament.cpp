@@ -72,6 +72,8 @@ struct pm_ctx {
     size_t w_bytes = 0;
     double* d_grad = nullptr;
     size_t grad_bytes = 0;
+    double* d_mom = nullptr;      // optimiser moments [2][K * n_samples]
+    size_t mom_bytes = 0;
     std::string err;
 };
 
@@ -726,6 +728,7 @@ pm_status pm_destroy(pm_ctx* ctx) {
         dfree(ctx->d_U);
         dfree(ctx->d_basis_grad);
         dfree(ctx->d_cheb);
+        dfree(ctx->d_mom);
         dfree(ctx->d_chain);
         dfree(ctx->d_gw);
         dfree(ctx->d_UT);
@@ -981,6 +984,46 @@ pm_status pm_trajectory_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_sa
     tp.out = out_dev;
     const hipError_t he = pm::launch_trajectory(ctx->geng.D, tp, st);
     if (he != hipSuccess) return hip_fail(ctx, he, "trajectory launch");
+    return PM_OK;
+}
+
+pm_status pm_grape_dev(pm_ctx* ctx, double* samples_dev, int64_t n_samples, double dt, const double* V_dev,
+                       int iters, double step, int optimizer, double* loss_dev, void* stream) {
+    pm_status s = check_prop_args(ctx, n_samples, dt);
+    if (s != PM_OK) return s;
+    s = check_grad_args(ctx);
+    if (s != PM_OK) return s;
+    if (iters < 0 || !(step > 0.0) || !std::isfinite(step) || (optimizer != PM_OPT_GD && optimizer != PM_OPT_ADAM))
+        return fail(ctx, PM_E_INVALID_ARG, "iters >= 0, step > 0, optimizer PM_OPT_GD or PM_OPT_ADAM");
+    if (!V_dev || !loss_dev || (ctx->n_ctrl > 0 && !samples_dev)) return fail(ctx, PM_E_INVALID_ARG, "null pointer");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    hipStream_t st = (hipStream_t)stream;
+    const int64_t n = ctx->n_ctrl * n_samples;
+    s = ensure(ctx, (void**)&ctx->d_W, &ctx->w_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "W");
+    if (s != PM_OK) return s;
+    s = ensure(ctx, (void**)&ctx->d_grad, &ctx->grad_bytes, sizeof(double) * (size_t)std::max<int64_t>(n, 1),
+               "gradient");
+    if (s != PM_OK) return s;
+    s = ensure(ctx, (void**)&ctx->d_mom, &ctx->mom_bytes, sizeof(double) * (size_t)std::max<int64_t>(2 * n, 1),
+               "optimiser moments");
+    if (s != PM_OK) return s;
+    hipError_t he = pm::launch_zero(ctx->d_mom, 2 * n, st);
+    if (he != hipSuccess) return hip_fail(ctx, he, "moment reset");
+    for (int it = 0; it <= iters; ++it) {
+        // forward (keeping checkpoints), loss and W from U(T)
+        s = launch_grad(ctx, samples_dev, n_samples, dt, nullptr, nullptr, st, true, false);
+        if (s != PM_OK) return s;
+        he = pm::launch_fidelity(ctx->d_UT, V_dev, (int)ctx->dim, ctx->d_W, loss_dev + it, st);
+        if (he != hipSuccess) return hip_fail(ctx, he, "fidelity");
+        if (it == iters) break;
+        // adjoint on the same forward, then the control update
+        s = launch_grad(ctx, samples_dev, n_samples, dt, ctx->d_W, ctx->d_grad, st, false, true);
+        if (s != PM_OK) return s;
+        he = pm::launch_update(samples_dev, ctx->d_grad, ctx->d_mom, ctx->d_mom + n, n, step, optimizer, it + 1,
+                               0.9, 0.999, 1e-8, st);
+        if (he != hipSuccess) return hip_fail(ctx, he, "control update");
+    }
     return PM_OK;
 }
 

@@ -61,6 +61,12 @@ struct TrajParams {
 
 hipError_t launch_trajectory(int D, const TrajParams& tp, hipStream_t stream);
 
+// Control optimisation helpers (engine_grape.hip).
+hipError_t launch_fidelity(const double* U, const double* V, int du, double* W, double* loss, hipStream_t st);
+hipError_t launch_update(double* c, const double* g, double* m, double* v, int64_t n, double step, int optimizer,
+                         int it, double b1, double b2, double eps, hipStream_t st);
+hipError_t launch_zero(double* a, int64_t n, hipStream_t st);
+
 // Batched instances: a packet is up to teams(D) consecutive chains of one
 // instance, run in lockstep by one block of the persistent batch kernel.
 struct BatchPacket {
