@@ -51,7 +51,7 @@ TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_tiles.h", "mfma_tree.h", "engine_com
 MEASURED_TRAFFIC = {"bytes": (2.0 * 4433.9375 + 1.0 * 4139.90625) * 1024.0,
                     "sources_sha256": "a3f44b7cf4ad98502eef67344c865ed86f89328369d947f21f69c0b1d2e96896",
                     "profile": "profiles/propagate_d16_random_qudit_traffic.md"}
-LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "trajectory", "grad", "batch", "cpu",
+LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "trajectory", "grad", "grape", "batch", "cpu",
         "fixed_error"]
 
 
@@ -379,6 +379,27 @@ def main():
         out["grad"] = {"workload": "qubit_register_d8_K4_N4096", "evals_per_s": 1e3 / wall_g,
                        "ms_per_eval": wall_g, "gpu_ms_per_eval": k_g, "params": int(wg.samples.size),
                        "loss": loss}
+
+    if "grape" in legs:
+        # the whole optimisation loop on the device: forward, loss, adjoint, Adam update
+        wq = synth.qubit_register()
+        cq = pm.Context(0, pm.PM_FP64)
+        cq.set_hamiltonian(wq.H0, wq.Hk, 2)
+        s0 = torch.from_numpy(wq.samples).to(dev)
+        sq = s0.clone()
+        Vq = torch.from_numpy(np.ascontiguousarray(wq.target)).to(dev)
+        iters = 20
+        lq = torch.empty(iters + 1, dtype=torch.float64, device=dev)
+
+        def grape_run():
+            sq.copy_(s0)
+            cq.grape_dev(sq, wq.h, Vq, iters, 0.05, pm.PM_OPT_ADAM, lq)
+        wall_q, k_q = time_launches(grape_run, 3, 1)
+        lh = lq.cpu().numpy()
+        out["grape"] = {"workload": "qubit_register_d8_K4_N4096, Adam", "iters": iters,
+                        "ms_per_iter": wall_q / iters, "iters_per_s": iters / (wall_q * 1e-3),
+                        "loss_first": float(lh[0]), "loss_last": float(lh[-1])}
+        cq.close()
 
     if "batch" in legs:
         # batched uneven instances: one persistent, graph-captured launch
