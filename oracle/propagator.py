@@ -22,6 +22,16 @@ U = exp(-i H t), Computational approach section):
     transposed, reversed-order view (reading recorded in the design doc).
     The commutator is formed from the assembled A1, A3, never through
     effective control Hamiltonians.
+  - commutator-free 4th order (the alternative the Magnus integrators
+    section names for higher orders, after Alvermann and Fehske; the
+    two-exponential scheme of Blanes and Moan): with M1 = integral of H
+    and M2 = (1/h) integral of (t - t_mid) H over the slice, both by
+    Simpson's rule on the same three samples,
+        U_j = exp(-i (M1/2 + 2 M2)) exp(-i (M1/2 - 2 M2))
+            = exp(-i (h/12)(-A1 + 4 A2 + 3 A3)) exp(-i (h/12)(3 A1 + 4 A2 - A3)),
+    whose combined exponent is M1 + i [M1, M2] up to O(h^5), the commutator
+    Magnus exponent above; no commutator of the controls is formed.
+    Scheme code CF4 (= 5) in the ``order`` argument.
 * slice propagators U_j = exp(-i G_j) by Hermitian eigendecomposition:
   G = Q diag(lam) Q^H  =>  exp(-i G) = Q diag(exp(-i lam)) Q^H (the
   decomposition route of the Matrix exponential section: for Hermitian
@@ -42,7 +52,11 @@ import numpy as np
 
 __all__ = [
     "hamiltonian_samples",
+    "CF4",
+    "n_slices",
     "magnus4_exponent",
+    "cf4_exponents",
+    "slice_propagators",
     "slice_exponents",
     "expm_minus_i",
     "ordered_product",
@@ -57,6 +71,14 @@ __all__ = [
 ]
 
 _CHUNK = 8192
+
+CF4 = 5   # scheme code of the commutator-free fourth-order integrator
+
+
+def n_slices(order: int, n_samples: int) -> int:
+    """Slices covered by n_samples samples: one sample per slice for the
+    midpoint rule, three per slice (shared ends, 2N + 1 in all) otherwise."""
+    return n_samples if order == 2 else (n_samples - 1) // 2
 
 
 def hamiltonian_samples(H0: np.ndarray, Hk: np.ndarray, samples: np.ndarray) -> np.ndarray:
@@ -95,6 +117,27 @@ def slice_exponents(H0, Hk, samples, h: float, order: int, start: int = 0, stop:
     raise ValueError("order must be 2 or 4")
 
 
+def cf4_exponents(H0, Hk, samples, h: float, start: int = 0, stop: int | None = None):
+    """(G_first, G_second) of the commutator-free 4th-order scheme for slices
+    [start, stop): U_j = exp(-i G_second[j]) exp(-i G_first[j]) with
+    G_first = (h/12)(3 A1 + 4 A2 - A3), G_second = (h/12)(-A1 + 4 A2 + 3 A3)."""
+    samples = np.asarray(samples, dtype=np.float64)
+    n = (samples.shape[1] - 1) // 2
+    stop = n if stop is None else stop
+    A = hamiltonian_samples(H0, Hk, samples[:, 2 * start: 2 * stop + 1])
+    A1, A2, A3 = A[0:-1:2], A[1::2], A[2::2]
+    return (h / 12.0) * (3.0 * A1 + 4.0 * A2 - A3), (h / 12.0) * (-A1 + 4.0 * A2 + 3.0 * A3)
+
+
+def slice_propagators(H0, Hk, samples, h: float, order: int, start: int = 0, stop: int | None = None):
+    """U_j for slices [start, stop): exp(-i G_j), or for CF4 the product of
+    its two exponentials (the second on the left)."""
+    if order == CF4:
+        Gf, Gs = cf4_exponents(H0, Hk, samples, h, start, stop)
+        return expm_minus_i(Gs) @ expm_minus_i(Gf)
+    return expm_minus_i(slice_exponents(H0, Hk, samples, h, order, start, stop))
+
+
 def expm_minus_i(G: np.ndarray) -> np.ndarray:
     """exp(-i G) for Hermitian G (batched), by eigendecomposition."""
     lam, Q = np.linalg.eigh(G)
@@ -113,13 +156,13 @@ def ordered_product(Us: np.ndarray, U: np.ndarray | None = None) -> np.ndarray:
 def propagate(H0, Hk, samples, h: float, order: int, return_slices: bool = False):
     """U(T) = U_{N-1} ... U_0 with U_j = exp(-i G_j).  Optionally all U_j."""
     samples = np.asarray(samples, dtype=np.float64)
-    n = samples.shape[1] if order == 2 else (samples.shape[1] - 1) // 2
+    n = n_slices(order, samples.shape[1])
     d = np.asarray(H0).shape[0]
     U = np.eye(d, dtype=np.complex128)
     slices = np.empty((n, d, d), dtype=np.complex128) if return_slices else None
     for s in range(0, n, _CHUNK):
         e = min(n, s + _CHUNK)
-        Uj = expm_minus_i(slice_exponents(H0, Hk, samples, h, order, s, e))
+        Uj = slice_propagators(H0, Hk, samples, h, order, s, e)
         if return_slices:
             slices[s:e] = Uj
         U = ordered_product(Uj, U)
@@ -131,13 +174,13 @@ def trajectory(H0, Hk, samples, h: float, order: int) -> np.ndarray:
     P_N = U(T)), taken sequentially: the time evolution at each slice
     boundary t_j = j h (eq. slices read at intermediate times)."""
     samples = np.asarray(samples, dtype=np.float64)
-    n = samples.shape[1] if order == 2 else (samples.shape[1] - 1) // 2
+    n = n_slices(order, samples.shape[1])
     d = np.asarray(H0).shape[0]
     out = np.empty((n + 1, d, d), dtype=np.complex128)
     out[0] = np.eye(d)
     for s in range(0, n, _CHUNK):
         e = min(n, s + _CHUNK)
-        Uj = expm_minus_i(slice_exponents(H0, Hk, samples, h, order, s, e))
+        Uj = slice_propagators(H0, Hk, samples, h, order, s, e)
         for q in range(e - s):
             out[s + q + 1] = Uj[q] @ out[s + q]
     return out
@@ -198,7 +241,9 @@ def control_gradient(H0, Hk, samples, h: float, order: int, W: np.ndarray):
     H0 = np.asarray(H0, np.complex128)
     Hk = np.asarray(Hk, np.complex128)
     samples = np.asarray(samples, np.float64)
-    n = samples.shape[1] if order == 2 else (samples.shape[1] - 1) // 2
+    if order == CF4:
+        return _control_gradient_cf4(H0, Hk, samples, h, W)
+    n = n_slices(order, samples.shape[1])
     d = H0.shape[0]
     G = slice_exponents(H0, Hk, samples, h, order)
     Us = expm_minus_i(G)
@@ -241,4 +286,41 @@ def control_gradient(H0, Hk, samples, h: float, order: int, W: np.ndarray):
         grad[k, 0:2 * n:2] += g0
         grad[k, 1:2 * n:2] += g1
         grad[k, 2:2 * n + 1:2] += g2
+    return U, grad
+
+
+def _control_gradient_cf4(H0, Hk, samples, h: float, W: np.ndarray):
+    """control_gradient for CF4: the 2N exponentials in product order
+    (first factor of slice j at position 2j, second at 2j + 1) take the place
+    of the slices; each exponent is linear in the samples,
+    dG_first/d(s0, s1, s2) = (h/12)(3, 4, -1) H_k and
+    dG_second/d(s0, s1, s2) = (h/12)(-1, 4, 3) H_k."""
+    n = n_slices(CF4, samples.shape[1])
+    d = H0.shape[0]
+    Gf, Gs = cf4_exponents(H0, Hk, samples, h)
+    G = np.empty((2 * n, d, d), np.complex128)
+    G[0::2] = Gf
+    G[1::2] = Gs
+    Us = expm_minus_i(G)
+    P = np.empty_like(Us)
+    acc = np.eye(d, dtype=np.complex128)
+    for v in range(2 * n):
+        P[v] = acc
+        acc = Us[v] @ acc
+    U = acc
+    S = np.empty_like(Us)
+    acc = np.eye(d, dtype=np.complex128)
+    for v in range(2 * n - 1, -1, -1):
+        S[v] = acc
+        acc = acc @ Us[v]
+    Lam = P @ np.conj(W.T)[None] @ S
+    Fg = frechet_expm_minus_i(G, Lam)
+    K = Hk.shape[0]
+    grad = np.zeros((K, samples.shape[1]))
+    for k in range(K):
+        t = np.real(np.einsum("nab,ba->n", Fg, Hk[k]))   # Re Tr(F_v H_k)
+        tf, ts = t[0::2], t[1::2]
+        grad[k, 0:2 * n:2] += (h / 12.0) * (3.0 * tf - ts)
+        grad[k, 1:2 * n:2] += (h / 12.0) * (4.0 * tf + 4.0 * ts)
+        grad[k, 2:2 * n + 1:2] += (h / 12.0) * (-tf + 3.0 * ts)
     return U, grad
