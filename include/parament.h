@@ -8,7 +8,9 @@
  * of the Computational approach section (Fig. 1):
  *   1. expand: one Hermitian exponent G_j per slice, by the midpoint rule
  *      (order 2) or by 4th-order commutator Magnus with Simpson quadrature
- *      (order 4, Magnus integrators section, eq. magnus_coeffs);
+ *      (order 4, Magnus integrators section, eq. magnus_coeffs), or -- the
+ *      commutator-free alternative the same section names -- two
+ *      exponents per slice without commutators (PM_ORDER_CF4);
  *   2. exponentiate all slices at once, U_j = exp(-i G_j), by scaling and
  *      squaring with a truncated Taylor series (Matrix exponential section);
  *   3. reduce U(T) = U_{N-1} ... U_1 U_0 (eq. slices) by chunked products and
@@ -25,7 +27,8 @@
  *     contiguous).  Order 2: n_samples = N, sample j is H's control value at
  *     the slice midpoint (j + 1/2) h.  Order 4: n_samples = 2N + 1 (odd,
  *     >= 3), sample i at t = i h / 2; slice j uses samples 2j, 2j+1, 2j+2.
- *   - dt is the slice width h for both orders (for order 4 the paper's
+ *     PM_ORDER_CF4 samples exactly as order 4.
+ *   - dt is the slice width h for every order (for order 4 the paper's
  *     sample spacing is h/2).
  *   - Product order: later slices multiply from the left.
  *   - The caller owns every buffer passed in.  pm_set_hamiltonian copies its
@@ -47,6 +50,20 @@ extern "C" {
 #endif
 
 typedef struct pm_ctx pm_ctx;
+
+/* Integrator codes of the `order` argument. */
+enum {
+    PM_ORDER_MIDPOINT = 2,  /* G_j = h H(t_j + h/2)                                 */
+    PM_ORDER_MAGNUS4 = 4,   /* commutator Magnus, eq. magnus_coeffs                 */
+    /* Commutator-free 4th order (the alternative to higher commutator Magnus
+     * that the Magnus integrators section names; the two-exponential scheme
+     * of Blanes and Moan): with A1, A2, A3 = H at the slice's three samples,
+     *   U_j = exp(-i (h/12)(-A1 + 4 A2 + 3 A3)) exp(-i (h/12)(3 A1 + 4 A2 - A3)),
+     * whose exponents are built from H0, H_k alone (basis 1 + n_ctrl).  The
+     * 2N exponentials are propagated as the factors of the product in
+     * order; per-slice output is not available (PM_E_INVALID_ARG).        */
+    PM_ORDER_CF4 = 5
+};
 
 typedef enum pm_status {
     PM_OK = 0,
@@ -95,7 +112,7 @@ pm_status pm_destroy(pm_ctx *ctx);
 
 /* Upload the drift H0 [dim][dim] and controls Hk [n_ctrl][dim][dim]
  * (complex128, Hermitian; Hk may be NULL when n_ctrl == 0) and choose the
- * integrator order (2: midpoint rule; 4: commutator Magnus).  For order 4 the
+ * integrator (PM_ORDER_MIDPOINT, PM_ORDER_MAGNUS4 or PM_ORDER_CF4).  For order 4 the
  * host forms the effective control Hamiltonians of eq. magnus_coeffs,
  * i[H0,H_k] and i[H_k,H_k'] (k<k'), all Hermitian, and uploads them too
  * (setHamiltonian of the PARAMENT library section).  Inputs are symmetrised
@@ -108,7 +125,7 @@ pm_status pm_set_hamiltonian(pm_ctx *ctx, int64_t dim, const double *H0,
  * samples: host [n_ctrl][n_samples] float64.  U_out: host [dim][dim]
  * complex128, receives U(T).  slices_out: NULL, or host [N][dim][dim]
  * receiving every U_j, complex128 for PM_FP64 and complex64 otherwise.
- * Synchronous. */
+ * Synchronous.  slices_out must be NULL for PM_ORDER_CF4. */
 pm_status pm_equiprop(pm_ctx *ctx, const double *samples, int64_t n_samples,
                       double dt, double *U_out, void *slices_out);
 
@@ -204,11 +221,11 @@ typedef struct pm_batch pm_batch;
 typedef struct pm_instance {
     int64_t dim;             /* 1..PM_MAX_DIM                                  */
     int64_t n_ctrl;          /* 0..8                                           */
-    int order;               /* 2 or 4                                         */
+    int order;               /* PM_ORDER_MIDPOINT, _MAGNUS4 or _CF4            */
     const double *H0;        /* host complex128 [dim][dim]                     */
     const double *Hk;        /* host complex128 [n_ctrl][dim][dim] (or NULL)   */
     const double *samples;   /* host float64 [n_ctrl][n_samples] (or NULL)     */
-    int64_t n_samples;       /* order 2: N; order 4: 2N + 1                    */
+    int64_t n_samples;       /* order 2: N; order 4 and CF4: 2N + 1            */
     double dt;               /* slice width h                                  */
 } pm_instance;
 
@@ -291,7 +308,7 @@ const char *pm_last_error(const pm_ctx *ctx);
 
 /* ---- host-only helpers: no GPU is touched ------------------------------ */
 
-/* Number of Hermitian basis matrices: 1 + n_ctrl (order 2), or
+/* Number of Hermitian basis matrices: 1 + n_ctrl (order 2 and CF4), or
  * 1 + 2 n_ctrl + n_ctrl (n_ctrl - 1) / 2 (order 4, eq. magnus_coeffs:
  * 3K/2 + K^2/2 effective controls besides H0).  -1 on bad arguments. */
 int64_t pm_basis_count(int64_t n_ctrl, int order);
@@ -307,6 +324,10 @@ pm_status pm_build_basis_host(int64_t dim, const double *H0, int64_t n_ctrl,
 
 /* Real weights w_{j,m} of slice j on that basis (the expand step):
  * order 2: w = h (1, c_1[j], ..., c_K[j]);
+ * CF4: `slice` numbers the 2N exponentials in product order, e = 2j + f
+ *   (f = 0 the first factor of slice j, f = 1 the second):
+ *   w_H0 = h/2, w_Hk = (h/12)(3 s0_k + 4 s1_k - s2_k) for f = 0 and
+ *   (h/12)(-s0_k + 4 s1_k + 3 s2_k) for f = 1;
  * order 4 with s0, s1, s2 = samples 2j, 2j+1, 2j+2:
  *   w_H0 = h, w_Hk = (h/6)(s0_k + 4 s1_k + s2_k),
  *   w_i[H0,Hk] = (h^2/12)(s2_k - s0_k),

@@ -24,6 +24,7 @@ PM_FP64, PM_FP32, PM_FP32_3M, PM_BF16_SPLIT = 0, 1, 2, 3
 PM_EXPM_TAYLOR, PM_EXPM_CHEBYSHEV = 0, 1
 PM_TRAJ_PROPAGATORS, PM_TRAJ_STATES, PM_TRAJ_DENSITY = 0, 1, 2
 PM_OPT_GD, PM_OPT_ADAM = 0, 1
+PM_ORDER_MIDPOINT, PM_ORDER_MAGNUS4, PM_ORDER_CF4 = 2, 4, 5
 MAX_CHEBYSHEV_DEGREE = 25
 PRECISIONS = {"fp64": PM_FP64, "fp32": PM_FP32, "fp32_3m": PM_FP32_3M, "bf16_split": PM_BF16_SPLIT}
 STATUS = ["PM_OK", "PM_E_INVALID_ARG", "PM_E_NOT_READY", "PM_E_NOT_HERMITIAN", "PM_E_OOM",
@@ -208,6 +209,7 @@ def plan_chebyshev(nu: float, precision: int = PM_FP64, max_degree: int = MAX_CH
 
 
 def n_slices(n_samples: int, order: int) -> int:
+    """Slices covered by n_samples samples (2N + 1 samples for order 4 and CF4)."""
     return n_samples if order == 2 else (n_samples - 1) // 2
 
 

@@ -41,13 +41,21 @@ __device__ __forceinline__ double readlane_d(double x, int l) {
     return __longlong_as_double(((long long)hi << 32) | (unsigned int)lo);
 }
 
-// Weight of basis matrix m in slice j (the expand step; eq. magnus_coeffs
-// for order 4 with the commutator sign of the standard product order).
+// Weight of basis matrix m in exponent j (the expand step; eq. magnus_coeffs
+// for order 4 with the commutator sign of the standard product order; for
+// the commutator-free scheme exponent j is factor j & 1 of slice j >> 1,
+// (h/12)(3 s0 + 4 s1 - s2) for the first and its mirror for the second).
 __device__ __forceinline__ double slice_weight(const PropParams& p, int64_t j, int m) {
     const double h = p.h;
-    if (m == 0) return h;
     const double* c = p.samples;
     const int64_t S = p.n_samples;
+    if (p.order == kOrderCF4) {
+        if (m == 0) return 0.5 * h;
+        const double* ck = c + (int64_t)(m - 1) * S + (j & ~(int64_t)1);
+        const double a = (j & 1) ? ck[2] : ck[0], b = (j & 1) ? ck[0] : ck[2];
+        return (h * (1.0 / 12.0)) * (3.0 * a + 4.0 * ck[1] - b);
+    }
+    if (m == 0) return h;
     if (p.order == 2) return h * c[(int64_t)(m - 1) * S + j];
     const int K = p.K;
     const double h2 = h * h * (1.0 / 12.0);
@@ -191,7 +199,8 @@ __device__ __forceinline__ void plan_cheb_lanes(const PropParams& p, double nu, 
 // lane gathers up to five samples of the slice and combines them with the
 // formula of its basis matrix.  Lanes m >= M get weight 0.
 struct WeightRecipe {
-    int kind;        // 0: H0 (h), 1: order-2 control, 2: Simpson, 3: commutator with H0, 4: pair, 5: none
+    int kind;        // 0: H0, 1: order-2 control, 2: Simpson, 3: commutator with H0, 4: pair, 5: none,
+                     // 6: commutator-free control
     int64_t xa, xb;  // sample offsets of controls a, b (before adding the slice position)
 };
 
@@ -211,6 +220,9 @@ __device__ __forceinline__ WeightRecipe weight_recipe(const PropParams& p, int m
         r.kind = 0;
     } else if (p.order == 2) {
         r.kind = 1;
+        r.xa = (int64_t)(m - 1) * S;
+    } else if (p.order == kOrderCF4) {
+        r.kind = 6;
         r.xa = (int64_t)(m - 1) * S;
     } else if (m <= K) {
         r.kind = 2;
@@ -233,6 +245,13 @@ __device__ __forceinline__ SliceSamples gather_samples(const PropParams& p, cons
     const double* c = p.samples;
     if (p.order == 2) {
         v.x0 = c[r.xa + j];
+    } else if (p.order == kOrderCF4) {
+        // the second factor reads the slice's samples mirrored
+        const double* a = c + r.xa + (j & ~(int64_t)1);
+        const bool second = (j & 1) != 0;
+        v.x0 = a[second ? 2 : 0];
+        v.x1 = a[1];
+        v.x2 = a[second ? 0 : 2];
     } else {
         const double* a = c + r.xa + 2 * j;
         const double* b = c + r.xb + 2 * j;
@@ -253,8 +272,10 @@ __device__ __forceinline__ double combine_weight(const PropParams& p, const Weig
     const double w2 = (h * (1.0 / 6.0)) * (v.x0 + 4.0 * v.x1 + v.x2);
     const double w3 = h2 * (v.x2 - v.x0);
     const double w4 = h2 * (v.x0 * v.y2 - v.x2 * v.y0);
+    const double w6 = (h * (1.0 / 12.0)) * (3.0 * v.x0 + 4.0 * v.x1 - v.x2);
     double w = 0.0;
-    w = r.kind == 0 ? h : w;
+    w = r.kind == 0 ? (p.order == kOrderCF4 ? 0.5 * h : h) : w;
+    w = r.kind == 6 ? w6 : w;
     w = r.kind == 1 ? w1 : w;
     w = r.kind == 2 ? w2 : w;
     w = r.kind == 3 ? w3 : w;

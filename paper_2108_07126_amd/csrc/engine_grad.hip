@@ -431,8 +431,11 @@ trajectory_mfma(TrajParams tp) {
     const double lth = lane_theta_of(p, L.lane);
     SliceSamples smp = gather_samples(p, wr, j0);
     const int64_t bofs = mfma_basis_index(D, 0, L.TI, L.TJ, 0, 0, L.lane);
+    // the commutator-free scheme has two exponentials per slice: a slice
+    // boundary is every second one
+    const int vs = p.order == kOrderCF4 ? 1 : 0;
     for (int64_t j = j0; j < j1; ++j) {
-        store_block<G>(tp.out + j * stride, S, du, cols, cols, L);
+        if ((j & vs) == 0) store_block<G>(tp.out + (j >> vs) * stride, S, du, cols, cols, L);
         const double wl = combine_weight(p, wr, smp);
         if (j + 1 < j1) smp = gather_samples(p, wr, j + 1);
         double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
@@ -461,7 +464,7 @@ trajectory_mfma(TrajParams tp) {
         S = mul2<G>(U, S, L, s0, s1);
         if (tp.kind == PM_TRAJ_DENSITY) S = mul_adjB<G>(S, U, L, s0, s1);
     }
-    if (j1 == p.n_slices) store_block<G>(tp.out + p.n_slices * stride, S, du, cols, cols, L);
+    if (j1 == p.n_slices) store_block<G>(tp.out + (p.n_slices >> vs) * stride, S, du, cols, cols, L);
 }
 
 // dL/d samples from dL/dw by the weight formulas of the expand step; one
@@ -479,6 +482,23 @@ __global__ void __launch_bounds__(256) samples_grad(GradParams gp, double* grad)
     const double* c = p.samples;
     if (p.order == 2) {
         grad[idx] = h * g[q * M + 1 + k];
+        return;
+    }
+    if (p.order == kOrderCF4) {
+        // exponents 2j and 2j+1 weigh the samples of slice j by
+        // (h/12)(3, 4, -1) and (h/12)(-1, 4, 3)
+        const double h12 = h * (1.0 / 12.0);
+        const int64_t NS = N >> 1;
+        double a = 0.0;
+        if (q & 1) {
+            const int64_t j = (q - 1) / 2;
+            a = 4.0 * (g[(2 * j) * M + 1 + k] + g[(2 * j + 1) * M + 1 + k]);
+        } else {
+            const int64_t jf = q / 2, jl = q / 2 - 1;   // first sample of jf, last of jl
+            if (jf < NS) a += 3.0 * g[(2 * jf) * M + 1 + k] - g[(2 * jf + 1) * M + 1 + k];
+            if (jl >= 0) a += 3.0 * g[(2 * jl + 1) * M + 1 + k] - g[(2 * jl) * M + 1 + k];
+        }
+        grad[idx] = h12 * a;
         return;
     }
     double acc = 0.0;

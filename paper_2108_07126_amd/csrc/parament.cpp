@@ -360,8 +360,21 @@ pm_status ensure(pm_ctx* ctx, void** ptr, size_t* have, size_t need, const char*
     return PM_OK;
 }
 
+bool order_ok(int order) {
+    return order == PM_ORDER_MIDPOINT || order == PM_ORDER_MAGNUS4 || order == PM_ORDER_CF4;
+}
+
+// Slices covered by n_samples samples (one per slice for the midpoint rule,
+// 2N + 1 otherwise).
 int64_t n_slices_of(int order, int64_t n_samples) {
     return order == 2 ? n_samples : (n_samples - 1) / 2;
+}
+
+// Exponentials the kernels evaluate: one per slice, two for CF4 (the
+// factors of each slice in product order).
+int64_t n_exps_of(int order, int64_t n_samples) {
+    const int64_t N = n_slices_of(order, n_samples);
+    return order == PM_ORDER_CF4 ? 2 * N : N;
 }
 
 pm_status check_prop_args(pm_ctx* ctx, int64_t n_samples, double dt) {
@@ -371,8 +384,8 @@ pm_status check_prop_args(pm_ctx* ctx, int64_t n_samples, double dt) {
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, PM_E_INVALID_ARG, "dt must be finite and > 0");
     if (ctx->order == 2 && n_samples < 1)
         return fail(ctx, PM_E_INVALID_ARG, "order 2 needs n_samples >= 1");
-    if (ctx->order == 4 && (n_samples < 3 || (n_samples % 2) == 0))
-        return fail(ctx, PM_E_INVALID_ARG, "order 4 needs an odd n_samples >= 3");
+    if (ctx->order != 2 && (n_samples < 3 || (n_samples % 2) == 0))
+        return fail(ctx, PM_E_INVALID_ARG, "orders 4 and CF4 need an odd n_samples >= 3");
     if (n_samples > (int64_t(1) << 40)) return fail(ctx, PM_E_INVALID_ARG, "n_samples too large");
     return PM_OK;
 }
@@ -413,13 +426,15 @@ int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N) {
     int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N, ctx->precision);
     c = ((c + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
     if (e.kind == pm::ENGINE_VALU && c > (int64_t(1) << 20)) c = int64_t(1) << 20;
+    // CF4: a chain starts at a slice boundary (an even exponential index)
+    if (ctx->order == PM_ORDER_CF4 && (c & 1)) ++c;
     return c;
 }
 
 // Workspace and kernel parameters of one propagation on engine e.
 pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, const double* basis, const double* d_samples,
                   int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out) {
-    const int64_t N = n_slices_of(ctx->order, n_samples);
+    const int64_t N = n_exps_of(ctx->order, n_samples);
     const int64_t chunk = effective_chunk(ctx, e, N);
     const int64_t chains = (N + chunk - 1) / chunk;
     const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
@@ -611,7 +626,7 @@ const char* pm_last_error(const pm_ctx* ctx) { return ctx ? ctx->err.c_str() : g
 
 int64_t pm_basis_count(int64_t n_ctrl, int order) {
     if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl) return -1;
-    if (order == 2) return 1 + n_ctrl;
+    if (order == 2 || order == PM_ORDER_CF4) return 1 + n_ctrl;
     if (order == 4) return 1 + 2 * n_ctrl + n_ctrl * (n_ctrl - 1) / 2;
     return -1;
 }
@@ -656,7 +671,7 @@ pm_status pm_plan_expm(double nu, int precision, int max_degree, int64_t n_slice
 pm_status pm_build_basis_host(int64_t dim, const double* H0, int64_t n_ctrl, const double* Hk,
                               int order, double* basis_out, double* norms_out) {
     if (dim < 1 || dim > PM_MAX_DIM || !H0 || n_ctrl < 0 || n_ctrl > pm::kMaxCtrl ||
-        (n_ctrl > 0 && !Hk) || (order != 2 && order != 4))
+        (n_ctrl > 0 && !Hk) || !order_ok(order))
         return PM_E_INVALID_ARG;
     std::vector<Mat> basis;
     std::vector<std::pair<int, int>> pairs;
@@ -677,14 +692,26 @@ pm_status pm_build_basis_host(int64_t dim, const double* H0, int64_t n_ctrl, con
 pm_status pm_slice_weights_host(int64_t n_ctrl, const double* samples, int64_t n_samples,
                                 double dt, int order, int64_t slice, double* weights_out) {
     if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl || (n_ctrl > 0 && !samples) || !weights_out ||
-        (order != 2 && order != 4))
+        !order_ok(order))
         return PM_E_INVALID_ARG;
-    if (order == 4 && (n_samples < 3 || (n_samples % 2) == 0)) return PM_E_INVALID_ARG;
-    const int64_t N = n_slices_of(order, n_samples);
+    if (order != 2 && (n_samples < 3 || (n_samples % 2) == 0)) return PM_E_INVALID_ARG;
+    const int64_t N = n_exps_of(order, n_samples);
     if (slice < 0 || slice >= N) return PM_E_INVALID_ARG;
     const int64_t K = n_ctrl, S = n_samples;
     const double h = dt;
     int64_t m = 0;
+    if (order == PM_ORDER_CF4) {
+        // factor f of slice j: (h/12)(3 s0 + 4 s1 - s2), mirrored for f = 1
+        const int64_t j = slice >> 1;
+        const bool second = (slice & 1) != 0;
+        weights_out[m++] = 0.5 * h;
+        for (int64_t k = 0; k < K; ++k) {
+            const double* c = samples + k * S + 2 * j;
+            const double a = second ? c[2] : c[0], b = second ? c[0] : c[2];
+            weights_out[m++] = (h / 12.0) * (3.0 * a + 4.0 * c[1] - b);
+        }
+        return PM_OK;
+    }
     weights_out[m++] = h;
     if (order == 2) {
         for (int64_t k = 0; k < K; ++k) weights_out[m++] = h * samples[k * S + slice];
@@ -790,7 +817,7 @@ pm_status pm_launch_shape(pm_ctx* ctx, int64_t n_samples, int64_t* chunk, int64_
                           int64_t* leaves) {
     if (!ctx || !chunk || !chains || !leaves) return ctx ? fail(ctx, PM_E_INVALID_ARG, "null output") : PM_E_INVALID_ARG;
     if (ctx->dim == 0) return fail(ctx, PM_E_NOT_READY, "pm_set_hamiltonian has not been called");
-    const int64_t N = n_slices_of(ctx->order, n_samples);
+    const int64_t N = n_exps_of(ctx->order, n_samples);
     if (N < 1) return fail(ctx, PM_E_INVALID_ARG, "bad n_samples for the integrator order");
     const int64_t c = effective_chunk(ctx, ctx->eng, N);
     *chunk = c;
@@ -805,7 +832,7 @@ pm_status pm_set_hamiltonian(pm_ctx* ctx, int64_t dim, const double* H0, int64_t
     if (ctx->broken) return fail(ctx, PM_E_DEVICE, "context unusable after a device error");
     if (dim < 1 || dim > PM_MAX_DIM) return fail(ctx, PM_E_INVALID_ARG, "dim must be in [1, 64]");
     if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl) return fail(ctx, PM_E_INVALID_ARG, "n_ctrl must be in [0, 8]");
-    if (order != 2 && order != 4) return fail(ctx, PM_E_INVALID_ARG, "order must be 2 or 4");
+    if (!order_ok(order)) return fail(ctx, PM_E_INVALID_ARG, "order must be 2, 4 or PM_ORDER_CF4");
     if (!H0 || (n_ctrl > 0 && !Hk)) return fail(ctx, PM_E_INVALID_ARG, "null Hamiltonian pointer");
     pm::EngineInfo e;
     if (!pm::pick_engine((int)dim, ctx->precision, &e))
@@ -887,6 +914,8 @@ pm_status pm_equiprop_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samp
     if (s != PM_OK) return s;
     if (!U_out_dev) return fail(ctx, PM_E_INVALID_ARG, "U_out is null");
     if (ctx->n_ctrl > 0 && !samples_dev) return fail(ctx, PM_E_INVALID_ARG, "samples is null");
+    if (slices_out_dev && ctx->order == PM_ORDER_CF4)
+        return fail(ctx, PM_E_INVALID_ARG, "per-slice output is not available with PM_ORDER_CF4");
     DeviceGuard g(ctx->device);
     if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
     return launch(ctx, samples_dev, n_samples, dt, U_out_dev, slices_out_dev, (hipStream_t)stream);
@@ -898,6 +927,8 @@ pm_status pm_equiprop(pm_ctx* ctx, const double* samples, int64_t n_samples, dou
     if (s != PM_OK) return s;
     if (!U_out) return fail(ctx, PM_E_INVALID_ARG, "U_out is null");
     if (ctx->n_ctrl > 0 && !samples) return fail(ctx, PM_E_INVALID_ARG, "samples is null");
+    if (slices_out && ctx->order == PM_ORDER_CF4)
+        return fail(ctx, PM_E_INVALID_ARG, "per-slice output is not available with PM_ORDER_CF4");
     const int64_t K = ctx->n_ctrl;
     for (int64_t i = 0; i < K * n_samples; ++i)
         if (!std::isfinite(samples[i])) return fail(ctx, PM_E_INVALID_ARG, "non-finite control sample");
@@ -1230,10 +1261,10 @@ pm_status pm_batch_set(pm_batch* b, const pm_instance* inst, int64_t n_inst) {
         const std::string tag = "instance " + std::to_string(i) + ": ";
         if (q.dim < 1 || q.dim > PM_MAX_DIM) return bfail(b, PM_E_INVALID_ARG, tag + "dim must be in [1, 64]");
         if (q.n_ctrl < 0 || q.n_ctrl > pm::kMaxCtrl) return bfail(b, PM_E_INVALID_ARG, tag + "n_ctrl in [0, 8]");
-        if (q.order != 2 && q.order != 4) return bfail(b, PM_E_INVALID_ARG, tag + "order must be 2 or 4");
+        if (!order_ok(q.order)) return bfail(b, PM_E_INVALID_ARG, tag + "order must be 2, 4 or PM_ORDER_CF4");
         if (!q.H0 || (q.n_ctrl > 0 && (!q.Hk || !q.samples))) return bfail(b, PM_E_INVALID_ARG, tag + "null pointer");
         if (!(q.dt > 0.0) || !std::isfinite(q.dt)) return bfail(b, PM_E_INVALID_ARG, tag + "dt must be finite and > 0");
-        if ((q.order == 2 && q.n_samples < 1) || (q.order == 4 && (q.n_samples < 3 || q.n_samples % 2 == 0)))
+        if ((q.order == 2 && q.n_samples < 1) || (q.order != 2 && (q.n_samples < 3 || q.n_samples % 2 == 0)))
             return bfail(b, PM_E_INVALID_ARG, tag + "bad n_samples for the order");
         for (int64_t k = 0; k < q.n_ctrl * q.n_samples; ++k)
             if (!std::isfinite(q.samples[k])) return bfail(b, PM_E_INVALID_ARG, tag + "non-finite sample");
@@ -1258,11 +1289,12 @@ pm_status pm_batch_set(pm_batch* b, const pm_instance* inst, int64_t n_inst) {
         hbasis.insert(hbasis.end(), lay.begin(), lay.end());
         soff[i] = (int64_t)hsamples.size();
         if (q.n_ctrl > 0) hsamples.insert(hsamples.end(), q.samples, q.samples + q.n_ctrl * q.n_samples);
-        const int64_t N = n_slices_of(q.order, q.n_samples);
+        const int64_t N = n_exps_of(q.order, q.n_samples);
         const int TEAMS = pm::batch_teams(D);
         int64_t chunk = b->chunk_cfg[class_index(D)];
         if (chunk <= 0) chunk = g_tune_batch_chunk[class_index(D)][b->precision];
         if (chunk <= 0) chunk = default_batch_chunk(D);
+        if (q.order == PM_ORDER_CF4 && (chunk & 1)) ++chunk;   // chains start at slice boundaries
         chunk = std::min(chunk, N);
         const int64_t chains = (N + chunk - 1) / chunk;
         const int64_t npk = (chains + TEAMS - 1) / TEAMS;

@@ -373,8 +373,9 @@ __device__ __forceinline__ Mat<D, T> exp_ch(Herm<D, T> x, int m, const double* j
     return U;
 }
 
-// The control samples one slice needs: K values (order 2) or the three
-// Simpson samples of each control (order 4), K <= KB.  Loaded for the next
+// The control samples one exponent needs: K values (order 2) or the three
+// Simpson samples of each control (order 4; for the commutator-free scheme
+// those of slice j >> 1, mirrored for its second factor), K <= KB.  Loaded for the next
 // slice while the current one is exponentiated; every load is issued
 // unconditionally (controls k >= K re-read control K-1) so the loads of a
 // slice go out back to back.
@@ -398,6 +399,12 @@ __device__ __forceinline__ SampleSet<ORD, KB> load_samples(const PropParams& p, 
         const int kk = min(k, p.K - 1);
         if constexpr (ORD == 2) {
             s.v[k] = c[(int64_t)kk * S + j];
+        } else if constexpr (ORD == kOrderCF4) {
+            const double* ck = c + (int64_t)kk * S + (j & ~(int64_t)1);
+            const bool second = (j & 1) != 0;
+            s.v[3 * k + 0] = ck[second ? 2 : 0];
+            s.v[3 * k + 1] = ck[1];
+            s.v[3 * k + 2] = ck[second ? 0 : 2];
         } else {
             const double* ck = c + (int64_t)kk * S + 2 * j;
             s.v[3 * k + 0] = ck[0];
@@ -429,6 +436,15 @@ __device__ __forceinline__ Herm<D, double> expand_slice(const PropParams& p, con
                 g.im[hidx<D>(r, cc)] = fma(w, b[(r * D + cc) * 2 + 1], g.im[hidx<D>(r, cc)]);
             }
     };
+    if constexpr (ORD == kOrderCF4) {
+        // one factor of the commutator-free step: (h/2) H0 + (h/12)(3 s0 + 4 s1 - s2) H_k
+        add(0.5 * h, 0);
+        const double h12 = h * (1.0 / 12.0);
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+            if (k < K) add(h12 * (3.0 * x.v[3 * k] + 4.0 * x.v[3 * k + 1] - x.v[3 * k + 2]), 1 + k);
+        return g;
+    }
     add(h, 0);
     if constexpr (ORD == 2) {
 #pragma unroll
@@ -907,8 +923,17 @@ hipError_t launch_valu_ord(const PropParams& p, hipStream_t stream) {
     return launch_valu_k<T, D, ORD, kMaxCtrl, OUT_NONE>(p, stream);
 }
 
+// The commutator-free scheme has no per-slice output (the host rejects it).
+template <typename T, int D>
+hipError_t launch_valu_cf4(const PropParams& p, hipStream_t stream) {
+    if (p.slices_out) return hipErrorInvalidValue;
+    if (p.K <= 2) return launch_valu_k<T, D, kOrderCF4, 2, OUT_NONE>(p, stream);
+    return launch_valu_k<T, D, kOrderCF4, kMaxCtrl, OUT_NONE>(p, stream);
+}
+
 template <typename T, int D>
 hipError_t launch_valu_one(const PropParams& p, hipStream_t stream) {
+    if (p.order == kOrderCF4) return launch_valu_cf4<T, D>(p, stream);
     return p.order == 2 ? launch_valu_ord<T, D, 2>(p, stream) : launch_valu_ord<T, D, 4>(p, stream);
 }
 

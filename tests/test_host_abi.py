@@ -48,6 +48,8 @@ def test_basis_count_matches_effective_control_count():
         assert pm.basis_count(K, 4) - 1 == (3 * K + K * K) // 2
     assert pm.basis_count(9, 2) == -1
     assert pm.basis_count(2, 3) == -1
+    for K in range(0, 9):   # the commutator-free scheme forms no commutators
+        assert pm.basis_count(K, pm.PM_ORDER_CF4) == 1 + K
 
 
 @pytest.mark.parametrize("order", [2, 4])
@@ -66,6 +68,23 @@ def test_expand_matches_oracle_slice_exponents(order, d, K):
         wt = pm.slice_weights_host(w.samples, w.h, order, j)
         G = np.tensordot(wt, B, axes=1)
         assert np.max(np.abs(G - Gref[j])) < 1e-14 * max(1.0, np.max(np.abs(Gref[j])))
+
+
+@pytest.mark.parametrize("d,K", [(2, 1), (5, 3), (8, 4)])
+def test_cf4_expand_matches_oracle_exponents(d, K):
+    """CF4: the weights of exponent 2j (2j + 1) on the basis H0, H_k give the
+    oracle's first (second) factor exponent of slice j."""
+    cf4 = pm.PM_ORDER_CF4
+    w = synth.random_system(d, K, n_slices=6, h=0.07, order=cf4, tag=d * 10 + K + 500)
+    B, _ = pm.build_basis_host(w.H0, w.Hk, cf4)
+    assert B.shape[0] == 1 + K
+    Gf, Gs = orc.cf4_exponents(w.H0, w.Hk, w.samples, w.h)
+    for j in range(w.n_slices):
+        for f, Gref in ((0, Gf[j]), (1, Gs[j])):
+            G = np.tensordot(pm.slice_weights_host(w.samples, w.h, cf4, 2 * j + f), B, axes=1)
+            assert np.max(np.abs(G - Gref)) < 1e-14 * max(1.0, np.max(np.abs(Gref)))
+    with pytest.raises(pm.ParamentError):
+        pm.slice_weights_host(w.samples, w.h, cf4, 2 * w.n_slices)
 
 
 def test_non_hermitian_rejected():
