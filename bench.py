@@ -51,7 +51,7 @@ TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_tiles.h", "mfma_tree.h", "engine_com
 MEASURED_TRAFFIC = {"bytes": (2.0 * 4433.9375 + 1.0 * 4139.90625) * 1024.0,
                     "sources_sha256": "a3f44b7cf4ad98502eef67344c865ed86f89328369d947f21f69c0b1d2e96896",
                     "profile": "profiles/propagate_d16_random_qudit_traffic.md"}
-LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "trajectory", "grad", "grape", "batch", "cpu",
+LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "cf4", "trajectory", "grad", "grape", "batch", "cpu",
         "fixed_error"]
 
 
@@ -230,6 +230,33 @@ def leg_chebyshev(pm, torch, dev, args, out):
     out["chebyshev"] = res
 
 
+def leg_cf4(pm, torch, dev, args, out):
+    """FP64 propagation with the commutator-free fourth-order step against
+    the commutator Magnus step at equal N on the headline system (3
+    controls) and on the same system with 8 controls, where the commutator
+    basis grows to 45 matrices against 9."""
+    import synth
+    res = {}
+    for K in (3, 8):
+        row = {}
+        for name, order in (("magnus4", 4), ("cf4", pm.PM_ORDER_CF4)):
+            w = synth.random_qudit(order=order, n_ctrl=K)
+            s_dev = torch.from_numpy(w.samples).to(dev)
+            U = torch.zeros((w.dim, w.dim), dtype=torch.complex128, device=dev)
+            ctx = pm.Context(0, pm.PM_FP64)
+            ctx.set_hamiltonian(w.H0, w.Hk, order)
+            _, k = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U), max(3, args.steps), 2)
+            row[name] = {"kernel_ms": k, "steps_per_s": w.n_slices / (k * 1e-3),
+                         "basis": pm.basis_count(K, order)}
+            row[name + "_U"] = U.cpu().numpy()
+            ctx.close()
+        row["rel_diff"] = float(np.linalg.norm(row["cf4_U"] - row["magnus4_U"]) / np.linalg.norm(row["magnus4_U"]))
+        del row["cf4_U"], row["magnus4_U"]
+        row["cf4_over_magnus4_time"] = row["cf4"]["kernel_ms"] / row["magnus4"]["kernel_ms"]
+        res[f"random_qudit_d16_K{K}_N2^17"] = row
+    out["cf4"] = res
+
+
 def leg_trajectory(pm, torch, dev, args, out):
     """All N+1 partial products of the headline workload (4 KiB each)."""
     import synth
@@ -359,6 +386,8 @@ def main():
         leg_copy(torch, dev, out)
     if "chebyshev" in legs:
         leg_chebyshev(pm, torch, dev, args, out)
+    if "cf4" in legs:
+        leg_cf4(pm, torch, dev, args, out)
     if "trajectory" in legs:
         leg_trajectory(pm, torch, dev, args, out)
 
