@@ -24,13 +24,15 @@
 namespace pm {
 namespace {
 
-// Waves per SIMD the register allocation must allow.
+// Waves per SIMD the register allocation must allow.  FP64 at D = 16 keeps
+// its whole series in registers; its launch (about one chain per two waves
+// of a SIMD) never asks for more than two waves per SIMD.
 template <typename T, int D>
 constexpr int min_waves_per_eu() {
-    return D == 64 ? 4 : (std::is_same<T, double>::value ? 3 : 4);
+    return D == 64 ? 4 : (std::is_same<T, double>::value ? (D == 16 ? 2 : 3) : 4);
 }
 
-template <typename T, int D, int NT, bool BL, int PMODE>
+template <typename T, int D, int NT, bool BL, int PMODE, bool CH>
 __global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
 __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, D>(), 8)))
 propagate_mfma(PropParams p) {
@@ -97,8 +99,7 @@ propagate_mfma(PropParams p) {
         // plan (FP64)
         const double nu = wave_uniform(team_norm1<G, T>(gre, gim, L, red));
         int m, s;
-        const bool cheb = kF64 && p.method == PM_EXPM_CHEBYSHEV;
-        if (cheb) plan_cheb_lanes(p, nu, L.lane, lcth, m, s);
+        if constexpr (CH) plan_cheb_lanes(p, nu, L.lane, lcth, m, s);
         else plan_expm_lanes(p, nu, L.lane, lth, m, s);
         m = wave_uniform(m);
         s = wave_uniform(s);
@@ -110,8 +111,24 @@ propagate_mfma(PropParams p) {
         }
         if constexpr (kF64) {
             // exponentiate, square, store, chain product Q <- U Q
-            Tile<T> U = cheb ? cheb_exp<G>(Gt, m, p.ctheta[m], p.cheb_j + m * (kMaxCheb + 1), L, s0, s1)
-                             : taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
+            Tile<T> U;
+            if constexpr (CH) {
+                U = cheb_exp<G>(Gt, m, p.ctheta[m], p.cheb_j + m * (kMaxCheb + 1), L, s0, s1);
+            } else if constexpr (G::TW == 1) {
+                // one-wave team: the series as the Hermitian pair C - i P and,
+                // without squarings, the chain product straight from it, all
+                // in registers
+                Tile<double> C, P;
+                taylor_parts_reg<double>(Gt, m, L, C, P);
+                if (s == 0) {
+                    if (p.slices_out) store_slice<G, T>(p, j, combine_cp<double>(C, P), L);
+                    Q = reg_mul_cp<double>(C, P, Q);
+                    continue;
+                }
+                U = combine_cp<double>(C, P);
+            } else {
+                U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
+            }
             if (s > 0) U = square_n<G, double>(U, s, L, s0);
             if (p.slices_out) store_slice<G, T>(p, j, U, L);
             team_sync<G>();
@@ -155,28 +172,37 @@ constexpr size_t lds_fixed_bytes() {
     return sizeof(double) * ((size_t)NT * 2 * G::SLOT + (size_t)G::TD * D + 2);
 }
 
-template <typename T, int D, int NT, bool BL, int PMODE>
+template <typename T, int D, int NT, bool BL, int PMODE, bool CH>
 hipError_t launch_one(const PropParams& p, hipStream_t stream) {
     using G = Geo<D, NT>;
     const size_t lds = lds_fixed_bytes<D, NT>() + (BL ? sizeof(double) * (size_t)p.M * G::TW * 512 : 0);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)propagate_mfma<T, D, NT, BL, PMODE>,
+        hipError_t e = hipFuncSetAttribute((const void*)propagate_mfma<T, D, NT, BL, PMODE, CH>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((propagate_mfma<T, D, NT, BL, PMODE>), dim3((unsigned)p.n_leaves), dim3(G::THREADS), lds,
+    hipLaunchKernelGGL((propagate_mfma<T, D, NT, BL, PMODE, CH>), dim3((unsigned)p.n_leaves), dim3(G::THREADS), lds,
                        stream, p);
     return hipGetLastError();
 }
 
-template <typename T, int D, int NT, int PMODE>
+template <typename T, int D, int NT, int PMODE, bool CH>
 hipError_t launch_bl(const PropParams& p, hipStream_t stream) {
     if constexpr (D == 16) {
-        if (p.basis_lds) return launch_one<T, D, NT, true, PMODE>(p, stream);
+        if (p.basis_lds) return launch_one<T, D, NT, true, PMODE, CH>(p, stream);
     }
-    return launch_one<T, D, NT, false, PMODE>(p, stream);
+    return launch_one<T, D, NT, false, PMODE, CH>(p, stream);
+}
+
+// The Chebyshev series is an FP64 method.
+template <typename T, int D, int NT, int PMODE>
+hipError_t launch_method(const PropParams& p, hipStream_t stream) {
+    if constexpr (std::is_same<T, double>::value) {
+        if (p.method == PM_EXPM_CHEBYSHEV) return launch_bl<T, D, NT, PMODE, true>(p, stream);
+    }
+    return launch_bl<T, D, NT, PMODE, false>(p, stream);
 }
 
 }  // namespace
@@ -187,9 +213,9 @@ constexpr int kNT16 = 4;
 template <typename T, int PMODE>
 hipError_t launch_dims(int D, const PropParams& p, hipStream_t stream) {
     switch (D) {
-        case 16: return launch_bl<T, 16, kNT16, PMODE>(p, stream);
-        case 32: return launch_bl<T, 32, 1, PMODE>(p, stream);
-        case 64: return launch_bl<T, 64, 1, PMODE>(p, stream);
+        case 16: return launch_method<T, 16, kNT16, PMODE>(p, stream);
+        case 32: return launch_method<T, 32, 1, PMODE>(p, stream);
+        case 64: return launch_method<T, 64, 1, PMODE>(p, stream);
         default: return hipErrorInvalidValue;
     }
 }

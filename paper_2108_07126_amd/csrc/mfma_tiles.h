@@ -319,6 +319,95 @@ __device__ __forceinline__ Tile<float> slot_mul_bf16s(const double* A, const dou
     return out;
 }
 
+// Complex products of one-wave tiles without leaving the lane.  In the
+// accumulator layout of the 16x16x4 MFMA a lane holds four rows of its
+// column (rows g + 4r in FP64, 4g + r in FP32, lane 16 g + j, column j), so
+// register r of B is B's k-slice r as the next MFMA wants it (k running
+// over the four rows that register r holds across the lane groups).  The
+// A-slice needs A[j][k] for those k, i.e. the transpose of what the lane
+// holds; for a Hermitian A that is conj(A[k][j]), register r of the lane
+// itself.  reg_mul takes the A-slices as (a_r - i a_i)[r]:
+//     sum_r (a_r - i a_i)[r] B[r]
+// by 3M: t1 = a_r Br, t2 = a_i Bi, t3 = (a_r - a_i)(Br + Bi);
+// Re = t1 + t2, Im = t3 - t1 + t2.
+template <typename T>
+__device__ __forceinline__ Tile<T> reg_mul(const T (&ar)[4], const T (&ai)[4], const Tile<T>& B) {
+    using V = typename V4<T>::type;
+    V t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        t1 = mfma16(ar[r], B.re[r], t1);
+        t2 = mfma16(ai[r], B.im[r], t2);
+        t3 = mfma16(ar[r] - ai[r], B.re[r] + B.im[r], t3);
+    }
+    Tile<T> out;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out.re[r] = t1[r] + t2[r];
+        out.im[r] = t3[r] - t1[r] + t2[r];
+    }
+    return out;
+}
+
+// A B for a Hermitian A (the A-slices are conj of the lane's own registers).
+template <typename T>
+__device__ __forceinline__ Tile<T> reg_mul_herm(const Tile<T>& A, const Tile<T>& B) {
+    return reg_mul<T>(A.re, A.im, B);
+}
+
+// (C - i P) B for Hermitian C and P: the A-slice of C - i P at (j, k) is
+// conj(C[k][j]) - i conj(P[k][j]) = (C_re - P_im) - i (C_im + P_re) of the
+// lane's own registers.
+template <typename T>
+__device__ __forceinline__ Tile<T> reg_mul_cp(const Tile<T>& C, const Tile<T>& P, const Tile<T>& B) {
+    T ar[4], ai[4];
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        ar[r] = C.re[r] - P.im[r];
+        ai[r] = C.im[r] + P.re[r];
+    }
+    return reg_mul<T>(ar, ai, B);
+}
+
+// C - i P as one tile.
+template <typename T>
+__device__ __forceinline__ Tile<T> combine_cp(const Tile<T>& C, const Tile<T>& P) {
+    Tile<T> U;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        U.re[r] = C.re[r] + P.im[r];
+        U.im[r] = C.im[r] - P.re[r];
+    }
+    return U;
+}
+
+// The degree-m Taylor polynomial of exp(-i G) for a (pre-scaled) Hermitian
+// one-wave tile, returned as the Hermitian pair exp(-i G) = C - i P with
+// C = C(Y) and P = G S'(Y), Y = G^2 (the cos / sin split of taylor_exp):
+// every product has a Hermitian left factor, so all of them stay in
+// registers.
+template <typename T>
+__device__ __forceinline__ void taylor_parts_reg(const Tile<T>& Gt, int m, const Lane& L, Tile<T>& C, Tile<T>& P) {
+    C = ident<T>(L);
+    if (m <= 1) {
+        P = Gt;
+        return;
+    }
+    const int qc = m / 2;        // highest power of Y in C
+    const int qs = (m - 1) / 2;  // highest power of Y in S'
+    const Tile<T> Y = reg_mul_herm<T>(Gt, Gt);
+    Tile<T> Sp = ident<T>(L);
+    axpy(C, cos_coef(1), Y);
+    if (qs >= 1) axpy(Sp, sin_coef(1), Y);
+    Tile<T> Yk = Y;
+    for (int k = 2; k <= qc; ++k) {
+        Yk = reg_mul_herm<T>(Y, Yk);
+        axpy(C, cos_coef(k), Yk);
+        if (k <= qs) axpy(Sp, sin_coef(k), Yk);
+    }
+    P = qs >= 1 ? reg_mul_herm<T>(Gt, Sp) : Gt;
+}
+
 // Product modes of the FP32 kernels: 0 four real products, 1 3M, 2 BF16-split 3M.
 template <class G, typename T, int PMODE>
 __device__ __forceinline__ Tile<T> mulT(const double* A, const double* B, const Lane& L) {
