@@ -24,12 +24,12 @@
 namespace pm {
 namespace {
 
-// Waves per SIMD the register allocation must allow.  FP64 at D = 16 keeps
-// its whole series in registers; its launch (about one chain per two waves
-// of a SIMD) never asks for more than two waves per SIMD.
+// Waves per SIMD the register allocation must allow.  D = 16 keeps its
+// whole series in registers; its launch (about two chains per SIMD) never
+// asks for more than two waves per SIMD.
 template <typename T, int D>
 constexpr int min_waves_per_eu() {
-    return D == 64 ? 4 : (std::is_same<T, double>::value ? (D == 16 ? 2 : 3) : 4);
+    return D == 16 ? 2 : (D == 64 ? 4 : (std::is_same<T, double>::value ? 3 : 4));
 }
 
 template <typename T, int D, int NT, bool BL, int PMODE, bool CH>
@@ -137,7 +137,32 @@ propagate_mfma(PropParams p) {
             team_sync<G>();
             Q = mulT<G, T, PMODE>(s0, s1, L);
         } else {
-            Tile<T> E = taylor_exp<G, T, PMODE, true>(Gt, m, L, s0, s1);
+            Tile<T> E;
+            if constexpr (G::TW == 1) {
+                // one-wave team: E = C - i P in registers and, without
+                // squarings, Q <- Q + E Q with E Q in registers too
+                Tile<T> C, P;
+                taylor_parts_reg<T, PMODE, true>(Gt, m, L, C, P);
+                if (s == 0) {
+                    if (p.slices_out) store_slice<G, T>(p, j, plus_ident<T>(combine_cp<T>(C, P), L), L);
+                    Tile<T> Qt;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        Qt.re[r] = (T)Qx.re[r];
+                        Qt.im[r] = (T)Qx.im[r];
+                    }
+                    const Tile<T> EQ = reg_mul_cp<T, PMODE>(C, P, Qt);
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        Qx.re[r] += (double)EQ.re[r];
+                        Qx.im[r] += (double)EQ.im[r];
+                    }
+                    continue;
+                }
+                E = combine_cp<T>(C, P);
+            } else {
+                E = taylor_exp<G, T, PMODE, true>(Gt, m, L, s0, s1);
+            }
             if (s > 0)
                 E = relayout<G, T>(square_excess_n<G>(relayout<G, double>(E, s0, L), s, L, s0), s0, L);
             if (p.slices_out) store_slice<G, T>(p, j, plus_ident<T>(E, L), L);

@@ -349,16 +349,83 @@ __device__ __forceinline__ Tile<T> reg_mul(const T (&ar)[4], const T (&ai)[4], c
     return out;
 }
 
+// The same product as four real products (the FP32 mode): with a = a_r - i a_i,
+// Re = sum a_r Br + a_i Bi and Im = sum a_r Bi - a_i Br in two chains.
+__device__ __forceinline__ Tile<float> reg_mul4(const float (&ar)[4], const float (&ai)[4], const Tile<float>& B) {
+    f4_t acc_re = {0, 0, 0, 0}, acc_im = {0, 0, 0, 0};
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        acc_re = mfma16(ar[r], B.re[r], acc_re);
+        acc_im = mfma16(ar[r], B.im[r], acc_im);
+        acc_re = mfma16(ai[r], B.im[r], acc_re);
+        acc_im = mfma16(-ai[r], B.re[r], acc_im);
+    }
+    Tile<float> out;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out.re[r] = acc_re[r];
+        out.im[r] = acc_im[r];
+    }
+    return out;
+}
+
+// The same product as 3M on BF16 hi/lo split operands (the BF16-split
+// mode): the 16x16x16 BF16 MFMA takes four consecutive k per lane group,
+// A[j][4 g + q] and B[4 g + q][j], which for one 16-wide tile are again the
+// lane's own four registers (rows 4 g + q of the FP32 accumulator layout).
+__device__ __forceinline__ Tile<float> reg_mul_bf16s(const float (&ar)[4], const float (&ai)[4],
+                                                     const Tile<float>& B) {
+    float as[4], bs[4];
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+        as[q] = ar[q] - ai[q];
+        bs[q] = B.re[q] + B.im[q];
+    }
+    s4_t arh, arl, aih, ail, ash, asl, brh, brl, bih, bil, bsh, bsl;
+    split_bf16x4(ar, arh, arl);
+    split_bf16x4(ai, aih, ail);
+    split_bf16x4(as, ash, asl);
+    split_bf16x4(B.re, brh, brl);
+    split_bf16x4(B.im, bih, bil);
+    split_bf16x4(bs, bsh, bsl);
+    f4_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+    t1 = mfma_bf16(arh, brh, t1);
+    t2 = mfma_bf16(aih, bih, t2);
+    t3 = mfma_bf16(ash, bsh, t3);
+    t1 = mfma_bf16(arh, brl, t1);
+    t2 = mfma_bf16(aih, bil, t2);
+    t3 = mfma_bf16(ash, bsl, t3);
+    t1 = mfma_bf16(arl, brh, t1);
+    t2 = mfma_bf16(ail, bih, t2);
+    t3 = mfma_bf16(asl, bsh, t3);
+    Tile<float> out;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out.re[r] = t1[r] + t2[r];
+        out.im[r] = t3[r] - t1[r] + t2[r];
+    }
+    return out;
+}
+
+// Register product in the engine's product mode: FP64 and FP32-3M as 3M,
+// FP32 as four real products, BF16 split as split 3M.
+template <typename T, int PMODE>
+__device__ __forceinline__ Tile<T> reg_mulP(const T (&ar)[4], const T (&ai)[4], const Tile<T>& B) {
+    if constexpr (std::is_same<T, double>::value || PMODE == 1) return reg_mul<T>(ar, ai, B);
+    else if constexpr (PMODE == 0) return reg_mul4(ar, ai, B);
+    else return reg_mul_bf16s(ar, ai, B);
+}
+
 // A B for a Hermitian A (the A-slices are conj of the lane's own registers).
-template <typename T>
+template <typename T, int PMODE = 0>
 __device__ __forceinline__ Tile<T> reg_mul_herm(const Tile<T>& A, const Tile<T>& B) {
-    return reg_mul<T>(A.re, A.im, B);
+    return reg_mulP<T, PMODE>(A.re, A.im, B);
 }
 
 // (C - i P) B for Hermitian C and P: the A-slice of C - i P at (j, k) is
 // conj(C[k][j]) - i conj(P[k][j]) = (C_re - P_im) - i (C_im + P_re) of the
 // lane's own registers.
-template <typename T>
+template <typename T, int PMODE = 0>
 __device__ __forceinline__ Tile<T> reg_mul_cp(const Tile<T>& C, const Tile<T>& P, const Tile<T>& B) {
     T ar[4], ai[4];
 #pragma unroll
@@ -366,7 +433,7 @@ __device__ __forceinline__ Tile<T> reg_mul_cp(const Tile<T>& C, const Tile<T>& P
         ar[r] = C.re[r] - P.im[r];
         ai[r] = C.im[r] + P.re[r];
     }
-    return reg_mul<T>(ar, ai, B);
+    return reg_mulP<T, PMODE>(ar, ai, B);
 }
 
 // C - i P as one tile.
@@ -385,27 +452,33 @@ __device__ __forceinline__ Tile<T> combine_cp(const Tile<T>& C, const Tile<T>& P
 // one-wave tile, returned as the Hermitian pair exp(-i G) = C - i P with
 // C = C(Y) and P = G S'(Y), Y = G^2 (the cos / sin split of taylor_exp):
 // every product has a Hermitian left factor, so all of them stay in
-// registers.
-template <typename T>
+// registers.  With EXCESS the identity term of C is left out (C - i P is
+// then exp(-i G) - I, accurate relative to ||G||).
+template <typename T, int PMODE = 0, bool EXCESS = false>
 __device__ __forceinline__ void taylor_parts_reg(const Tile<T>& Gt, int m, const Lane& L, Tile<T>& C, Tile<T>& P) {
-    C = ident<T>(L);
+    if constexpr (EXCESS) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) C.re[r] = C.im[r] = T(0);
+    } else {
+        C = ident<T>(L);
+    }
     if (m <= 1) {
         P = Gt;
         return;
     }
     const int qc = m / 2;        // highest power of Y in C
     const int qs = (m - 1) / 2;  // highest power of Y in S'
-    const Tile<T> Y = reg_mul_herm<T>(Gt, Gt);
+    const Tile<T> Y = reg_mul_herm<T, PMODE>(Gt, Gt);
     Tile<T> Sp = ident<T>(L);
     axpy(C, cos_coef(1), Y);
     if (qs >= 1) axpy(Sp, sin_coef(1), Y);
     Tile<T> Yk = Y;
     for (int k = 2; k <= qc; ++k) {
-        Yk = reg_mul_herm<T>(Y, Yk);
+        Yk = reg_mul_herm<T, PMODE>(Y, Yk);
         axpy(C, cos_coef(k), Yk);
         if (k <= qs) axpy(Sp, sin_coef(k), Yk);
     }
-    P = qs >= 1 ? reg_mul_herm<T>(Gt, Sp) : Gt;
+    P = qs >= 1 ? reg_mul_herm<T, PMODE>(Gt, Sp) : Gt;
 }
 
 // Product modes of the FP32 kernels: 0 four real products, 1 3M, 2 BF16-split 3M.
