@@ -6,19 +6,108 @@
 namespace pm {
 namespace {
 
-// Pairwise product tree over the chain products (FP64).  Level l holds
-// cnt_l nodes; node i pairs with i^1 (odd index = later slices = left
-// factor); an unpaired last node moves up unchanged.  The first team to reach
-// a pair leaves its product in `nodes` and exits; the second multiplies.
-// With p.store_nodes every node of every level (carried ones and the root
-// included) is left in `nodes`, so node (l, i) holds the product over leaves
-// [i 2^l, (i+1) 2^l) for the gradient's checkpoints.
-// With active == false (a multi-wave team that only keeps another team's
-// barriers) the wave follows the same barriers and tickets but touches no
+// Product trees over the chain (or block) products, in FP64.  With
+// active == false (a multi-wave team that only keeps another team's
+// barriers) a wave follows the same barriers and tickets but touches no
 // memory and writes nothing.
+
+// Publish this team's node (stored by the caller) and take a ticket on
+// counter c: one agent-scope release before the ticket, and an acquire only
+// for the team that goes on (ticket `proceed`).  These fences write back /
+// invalidate the XCD's L2, so each is issued once per team where needed.
+// Returns the ticket (the same value in every wave of the team).
 template <class G>
-__device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
-                            double* s0, double* s1, int* tick, bool active = true) {
+__device__ __forceinline__ unsigned publish_ticket(const PropParams& p, int64_t c, unsigned proceed, const Lane& L,
+                                                   int* tick, bool active) {
+    unsigned t;
+    if constexpr (G::TW == 1) {
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+        unsigned v = 0;
+        if (L.lane == 0) v = atomicAdd(&p.counters[c], 1u);
+        t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(v, 0));
+        if (t == proceed) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+    } else {
+        __syncthreads();   // every wave's tile of the node is stored
+        if (active && L.wt == 0 && L.lane == 0) {
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+            const unsigned v = atomicAdd(&p.counters[c], 1u);
+            if (v == proceed) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+            *tick = (int)v;
+        }
+        __syncthreads();
+        t = (unsigned)*tick;
+        __syncthreads();
+    }
+    return t;
+}
+
+// The root's product into U_out (the d x d corner of the D x D tile set).
+template <class G>
+__device__ __forceinline__ void store_root(const PropParams& p, const Tile<double>& Q, const Lane& L) {
+    const int col = 16 * L.TJ + L.j;
+    if (col < p.du) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int row = 16 * L.TI + crow<double>(L.g, r);
+            if (row < p.du) {
+                p.U_out[(row * p.du + col) * 2 + 0] = Q.re[r];
+                p.U_out[(row * p.du + col) * 2 + 1] = Q.im[r];
+            }
+        }
+    }
+}
+
+// Fan-in of the product tree when no node is kept: the last of up to kFanIn
+// consecutive nodes of a level to arrive multiplies them (later nodes on the
+// left) and goes on; a group of one moves up unchanged.  Against the
+// pairwise tree this publishes each node once and acquires once per group
+// (for 8 leaves 8 releases and 1 acquire instead of 14 and 7) in a third of
+// the levels.
+constexpr int kFanIn = 8;
+
+template <class G>
+__device__ void tree_reduce_groups(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
+                                   double* s0, double* s1, int* tick, bool active) {
+    const int64_t NN = (int64_t)G::D * G::D * 2;
+    int64_t idx = leaf, cnt = p.n_leaves, off = 0;
+    while (cnt > 1) {
+        const int64_t pcnt = (cnt + kFanIn - 1) / kFanIn, poff = off + cnt, grp = idx / kFanIn;
+        const int64_t first = grp * kFanIn;
+        const int64_t members = min(cnt, first + kFanIn) - first;
+        if (members > 1) {
+            if (active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
+            const unsigned t = publish_ticket<G>(p, poff + grp, (unsigned)(members - 1), L, tick, active);
+            if (t != (unsigned)(members - 1)) return;
+            if (active && L.lane == 0 && L.wt == 0) atomicExch(&p.counters[poff + grp], 0u);
+            const int64_t last = first + members - 1;
+            Tile<double> P = (last == idx || !active) ? Q : node_load<G>(p.nodes + (off + last) * NN, L);
+            for (int64_t k = last - 1; k >= first; --k) {
+                const Tile<double> X = (k == idx || !active) ? Q : node_load<G>(p.nodes + (off + k) * NN, L);
+                team_sync<G>();
+                slot_store<G, double>(s0, P, L);   // left factor: later slices
+                slot_store<G, double>(s1, X, L);
+                team_sync<G>();
+                P = slot_mul<G, double>(s0, s1, L);
+            }
+            Q = P;
+        }
+        idx = grp;
+        off = poff;
+        cnt = pcnt;
+    }
+    if (active) store_root<G>(p, Q, L);
+}
+
+// Pairwise tree.  Level l holds cnt_l nodes; node i pairs with i^1 (odd
+// index = later slices = left factor); an unpaired last node moves up
+// unchanged.  The first team to reach a pair leaves its product in `nodes`
+// and exits; the second multiplies.  With p.store_nodes every node of every
+// level (carried ones and the root included) is left in `nodes`, so node
+// (l, i) holds the product over leaves [i 2^l, (i+1) 2^l) for the gradient's
+// checkpoints.
+template <class G>
+__device__ void tree_reduce_pairs(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
+                                  double* s0, double* s1, int* tick, bool active) {
     const int64_t NN = (int64_t)G::D * G::D * 2;
     int64_t idx = leaf, cnt = p.n_leaves, off = 0;
     while (cnt > 1) {
@@ -27,31 +116,8 @@ __device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, c
         if (carry && p.store_nodes && active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
         if (!carry) {
             if (active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
-            // publish the node with one agent-scope release before the
-            // ticket, and acquire only as the second arriver of a pair:
-            // these fences write back / invalidate the XCD's L2, so each is
-            // issued once per team where it is needed
-            unsigned t;
-            if constexpr (G::TW == 1) {
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                unsigned v = 0;
-                if (L.lane == 0) v = atomicAdd(&p.counters[poff + par], 1u);
-                t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(v, 0));
-                if (t == 0) return;
-                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            } else {
-                __syncthreads();   // every wave's tile of the node is stored
-                if (active && L.wt == 0 && L.lane == 0) {
-                    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
-                    const unsigned v = atomicAdd(&p.counters[poff + par], 1u);
-                    if (v != 0) __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    *tick = (int)v;
-                }
-                __syncthreads();
-                t = (unsigned)*tick;
-                __syncthreads();
-                if (t == 0) return;
-            }
+            const unsigned t = publish_ticket<G>(p, poff + par, 1u, L, tick, active);
+            if (t == 0) return;
             if (active && L.lane == 0 && L.wt == 0) atomicExch(&p.counters[poff + par], 0u);
             const Tile<double> other = active ? node_load<G>(p.nodes + (off + (idx ^ 1)) * NN, L) : Q;
             team_sync<G>();
@@ -66,17 +132,17 @@ __device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, c
     }
     if (!active) return;
     if (p.store_nodes) node_store<G>(p.nodes + off * NN, Q, L);
-    const int col = 16 * L.TJ + L.j;
-    if (col < p.du) {
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const int row = 16 * L.TI + crow<double>(L.g, r);
-            if (row < p.du) {
-                p.U_out[(row * p.du + col) * 2 + 0] = Q.re[r];
-                p.U_out[(row * p.du + col) * 2 + 1] = Q.im[r];
-            }
-        }
-    }
+    store_root<G>(p, Q, L);
+}
+
+// The product tree over the chain (or block) products: pairwise when every
+// node is kept (the gradient's and the trajectory's checkpoints are its
+// aligned power-of-two nodes), else with fan-in kFanIn.
+template <class G>
+__device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
+                            double* s0, double* s1, int* tick, bool active = true) {
+    if (p.store_nodes) tree_reduce_pairs<G>(p, leaf, Q, L, s0, s1, tick, active);
+    else tree_reduce_groups<G>(p, leaf, Q, L, s0, s1, tick, active);
 }
 
 }  // namespace

@@ -408,18 +408,21 @@ int tune_class(int D) {
 
 // Chain length: about one chain per resident wave team (or the tuned count),
 // in whole units.
-int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision) {
+int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool keep_nodes) {
     int64_t target = (int64_t)e.resident_chains;
     const int tc = tune_class(e.D);
     if (tc >= 0 && precision >= 0 && precision < 4 && g_tune_chains[tc][precision] > 0)
         target = g_tune_chains[tc][precision];
     int64_t c = (N + target - 1) / target;
     if (c < 1) c = 1;
-    // MFMA chains of at least four slices: below that the product tree's
-    // per-leaf publication (an agent-scope release and acquire per node)
-    // costs more than the parallelism gains (N = 4096: 1024 chains of four
-    // beat 2048 of two by 13 % in the gradient and 26 % in the forward pass)
-    if (e.kind == pm::ENGINE_MFMA && c < 4) c = 4;
+    // Short MFMA chains: below eight slices (four for the gradient's and the
+    // trajectory's forward pass, whose backward or replay has more work per
+    // slice) the product tree's per-leaf publication (an agent-scope release
+    // and acquire per node) costs more than the parallelism gains.  Measured
+    // on the d=16 workload: N = 8192, chains of 8 beat 4 by 16 %; N = 4096
+    // gradient, chains of 4 beat 2 by 13 % and 8 by 30 %.
+    const int64_t cmin = keep_nodes ? 4 : 8;
+    if (e.kind == pm::ENGINE_MFMA && c < cmin) c = cmin;
     const int64_t u = e.chunk_unit;
     return ((c + u - 1) / u) * u;
 }
@@ -427,8 +430,8 @@ int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision) {
 // Chain length of a propagation: the user's, else the automatic one; whole
 // units, and for the VALU engine at most 2^20 slices (its per-slice output
 // addresses a chain's slices with 32-bit offsets).
-int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N) {
-    int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N, ctx->precision);
+int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, bool keep_nodes = false) {
+    int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N, ctx->precision, keep_nodes);
     c = ((c + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
     if (e.kind == pm::ENGINE_VALU && c > (int64_t(1) << 20)) c = int64_t(1) << 20;
     // CF4: a chain starts at a slice boundary (an even exponential index)
@@ -437,10 +440,10 @@ int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N) {
 }
 
 // Workspace and kernel parameters of one propagation on engine e.
-pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, const double* basis, const double* d_samples,
+pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, bool keep_nodes, const double* basis, const double* d_samples,
                   int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out) {
     const int64_t N = n_exps_of(ctx->order, n_samples);
-    const int64_t chunk = effective_chunk(ctx, e, N);
+    const int64_t chunk = effective_chunk(ctx, e, N, keep_nodes);
     const int64_t chains = (N + chunk - 1) / chunk;
     const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
     const size_t node_bytes = (size_t)e.D * e.D * 16;
@@ -494,7 +497,7 @@ pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, const double* basis, con
 pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt, double* d_U,
                  void* d_slices, hipStream_t stream) {
     pm::PropParams p;
-    pm_status st = prepare(ctx, ctx->eng, ctx->d_basis, d_samples, n_samples, dt, d_U, d_slices, &p);
+    pm_status st = prepare(ctx, ctx->eng, false, ctx->d_basis, d_samples, n_samples, dt, d_U, d_slices, &p);
     if (st != PM_OK) return st;
     hipError_t he = pm::launch_propagate(ctx->eng, ctx->precision, p, stream);
     if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
@@ -512,7 +515,7 @@ pm_status forward_keep(pm_ctx* ctx, const double* d_samples, int64_t n_samples, 
     pm::PropParams& p = *out;
     pm_status st = ensure(ctx, (void**)&ctx->d_UT, &ctx->ut_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "U(T)");
     if (st != PM_OK) return st;
-    st = prepare(ctx, e, basis, d_samples, n_samples, dt, ctx->d_UT, nullptr, &p);
+    st = prepare(ctx, e, true, basis, d_samples, n_samples, dt, ctx->d_UT, nullptr, &p);
     if (st != PM_OK) return st;
     p.method = PM_EXPM_TAYLOR;   // the adjoint and the trajectory use the Taylor evaluation
     st = ensure(ctx, (void**)&ctx->d_chain, &ctx->chain_bytes, (size_t)p.n_chains * e.D * e.D * 16,
