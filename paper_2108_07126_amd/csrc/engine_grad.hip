@@ -230,19 +230,22 @@ __device__ Tile<double> chain_checkpoint(const PropParams& p, int64_t chain, con
                                          double* s1) {
     const int64_t NN = (int64_t)G::D * G::D * 2;
     Tile<double> P = ident<double>(L);
+    // leaves [0, b) as aligned tree nodes, earliest first: at level l the
+    // first d_l nodes of b's group, d_l the base-kFanIn digit l of b
     const int64_t b = chain / G::NT;
     int nlev = 0;
-    for (int64_t cnt = p.n_leaves; cnt > 1; cnt = (cnt + 1) >> 1) ++nlev;
+    for (int64_t cnt = p.n_leaves; cnt > 1; cnt = (cnt + kFanIn - 1) / kFanIn) ++nlev;
     for (int l = nlev; l >= 0; --l) {
-        if ((b >> l) & 1) {
-            int64_t off = 0, cnt = p.n_leaves;
-            for (int q = 0; q < l; ++q) {
-                off += cnt;
-                cnt = (cnt + 1) >> 1;
-            }
-            const Tile<double> nd = node_load<G>(p.nodes + (off + (b >> l) - 1) * NN, L);
-            P = mul2<G>(nd, P, L, s0, s1);
+        const int64_t d = (b >> (kFanInLog2 * l)) & (kFanIn - 1);
+        if (d == 0) continue;
+        int64_t off = 0, cnt = p.n_leaves;
+        for (int q = 0; q < l; ++q) {
+            off += cnt;
+            cnt = (cnt + kFanIn - 1) / kFanIn;
         }
+        const int64_t first = (b >> (kFanInLog2 * (l + 1))) << kFanInLog2;
+        for (int64_t k = 0; k < d; ++k)
+            P = mul2<G>(node_load<G>(p.nodes + (off + first + k) * NN, L), P, L, s0, s1);
     }
     for (int64_t c = b * G::NT; c < chain; ++c)
         P = mul2<G>(node_load<G>(p.chain_out + c * NN, L), P, L, s0, s1);

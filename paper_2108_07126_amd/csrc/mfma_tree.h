@@ -57,13 +57,15 @@ __device__ __forceinline__ void store_root(const PropParams& p, const Tile<doubl
     }
 }
 
-// Fan-in of the product tree when no node is kept: the last of up to kFanIn
-// consecutive nodes of a level to arrive multiplies them (later nodes on the
-// left) and goes on; a group of one moves up unchanged.  Against the
-// pairwise tree this publishes each node once and acquires once per group
-// (for 8 leaves 8 releases and 1 acquire instead of 14 and 7) in a third of
-// the levels.
-constexpr int kFanIn = 8;
+// Product tree with fan-in kFanIn: the last of up to kFanIn consecutive
+// nodes of a level to arrive multiplies them (later nodes on the left) and
+// goes on; a group of one moves up unchanged.  Against a pairwise tree this
+// publishes each node once and acquires once per group (for 8 leaves 8
+// releases and 1 acquire instead of 14 and 7) in a third of the levels.
+// With p.store_nodes every node of every level (carried ones and the root
+// included) is left in `nodes`: node (l, i) holds the product over leaves
+// [i 8^l, (i+1) 8^l), the aligned blocks the gradient's and the
+// trajectory's checkpoints are assembled from.
 
 template <class G>
 __device__ void tree_reduce_groups(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
@@ -74,6 +76,7 @@ __device__ void tree_reduce_groups(const PropParams& p, int64_t leaf, Tile<doubl
         const int64_t pcnt = (cnt + kFanIn - 1) / kFanIn, poff = off + cnt, grp = idx / kFanIn;
         const int64_t first = grp * kFanIn;
         const int64_t members = min(cnt, first + kFanIn) - first;
+        if (members == 1 && p.store_nodes && active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
         if (members > 1) {
             if (active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
             const unsigned t = publish_ticket<G>(p, poff + grp, (unsigned)(members - 1), L, tick, active);
@@ -95,54 +98,16 @@ __device__ void tree_reduce_groups(const PropParams& p, int64_t leaf, Tile<doubl
         off = poff;
         cnt = pcnt;
     }
-    if (active) store_root<G>(p, Q, L);
-}
-
-// Pairwise tree.  Level l holds cnt_l nodes; node i pairs with i^1 (odd
-// index = later slices = left factor); an unpaired last node moves up
-// unchanged.  The first team to reach a pair leaves its product in `nodes`
-// and exits; the second multiplies.  With p.store_nodes every node of every
-// level (carried ones and the root included) is left in `nodes`, so node
-// (l, i) holds the product over leaves [i 2^l, (i+1) 2^l) for the gradient's
-// checkpoints.
-template <class G>
-__device__ void tree_reduce_pairs(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
-                                  double* s0, double* s1, int* tick, bool active) {
-    const int64_t NN = (int64_t)G::D * G::D * 2;
-    int64_t idx = leaf, cnt = p.n_leaves, off = 0;
-    while (cnt > 1) {
-        const int64_t pcnt = (cnt + 1) >> 1, poff = off + cnt, par = idx >> 1;
-        const bool carry = (idx == cnt - 1) && (cnt & 1);
-        if (carry && p.store_nodes && active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
-        if (!carry) {
-            if (active) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
-            const unsigned t = publish_ticket<G>(p, poff + par, 1u, L, tick, active);
-            if (t == 0) return;
-            if (active && L.lane == 0 && L.wt == 0) atomicExch(&p.counters[poff + par], 0u);
-            const Tile<double> other = active ? node_load<G>(p.nodes + (off + (idx ^ 1)) * NN, L) : Q;
-            team_sync<G>();
-            slot_store<G, double>(s0, (idx & 1) ? Q : other, L);   // left factor: later slices
-            slot_store<G, double>(s1, (idx & 1) ? other : Q, L);
-            team_sync<G>();
-            Q = slot_mul<G, double>(s0, s1, L);
-        }
-        idx = par;
-        off = poff;
-        cnt = pcnt;
-    }
     if (!active) return;
     if (p.store_nodes) node_store<G>(p.nodes + off * NN, Q, L);
     store_root<G>(p, Q, L);
 }
 
-// The product tree over the chain (or block) products: pairwise when every
-// node is kept (the gradient's and the trajectory's checkpoints are its
-// aligned power-of-two nodes), else with fan-in kFanIn.
+// The product tree over the chain (or block) products.
 template <class G>
 __device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
                             double* s0, double* s1, int* tick, bool active = true) {
-    if (p.store_nodes) tree_reduce_pairs<G>(p, leaf, Q, L, s0, s1, tick, active);
-    else tree_reduce_groups<G>(p, leaf, Q, L, s0, s1, tick, active);
+    tree_reduce_groups<G>(p, leaf, Q, L, s0, s1, tick, active);
 }
 
 }  // namespace
