@@ -175,10 +175,33 @@ def leg_d64(pm, torch, dev, args, out):
     return w, Ug
 
 
+def sampled_flops(pm, w, precision, sample: int = 65536) -> float:
+    """Algorithmic flops of a propagation at the user dimension d: per slice
+    8 d^3 per complex product (Taylor products, squarings, chain) plus
+    4 M d^2 for the expand, the planner's (m, s) taken on the first `sample`
+    slices' ||G_j||_1 and scaled to all N (order-2 workloads)."""
+    B, _ = pm.build_basis_host(w.H0, w.Hk, w.order)
+    M, d, n = B.shape[0], w.dim, w.n_slices
+    ns = min(n, sample)
+    Wt = np.zeros((ns, M))
+    Wt[:, 0] = w.h
+    Wt[:, 1:1 + w.n_ctrl] = w.h * w.samples[:, :ns].T
+    G = np.tensordot(Wt, B, axes=1)
+    nu = np.max(np.sum(np.abs(G), axis=1), axis=1)
+    prods = 0
+    for x in nu:
+        m, s_ = pm.plan_expm(float(x), precision, n_slices=n)
+        prods += taylor_products(m) + s_ + 1
+    return (8.0 * d ** 3 * prods + 4.0 * M * d * d * ns) * (n / ns)
+
+
 def leg_small(pm, torch, dev, args, out):
-    """Dims 2, 4 and 8 with every U_j written out: HBM-bound.  Algorithmic
-    bytes per slice = the slice's control samples (8 B each) + its
-    propagator (d^2 complex entries, 16 B in FP64 and 8 B otherwise)."""
+    """Dims 2, 4 and 8 with every U_j written out.  Algorithmic bytes per
+    slice = the slice's control samples (8 B each) + its propagator (d^2
+    complex entries, 16 B in FP64 and 8 B otherwise); algorithmic flops from
+    sampled_flops.  The roofline time is the larger of bytes / 8 TB/s and
+    flops / the precision's vector/MFMA peak: dims 2 and 4 sit at or below
+    the FP64 ridge (9.8 flop/B), dim 8 far above it (compute-bound)."""
     import synth
     cases = [("driven_qubit_d2_N2^26", synth.driven_qubit(n_slices=2 ** 26, h=0.01)),
              ("random_d4_K2_N2^24", synth.random_system(4, 2, n_slices=2 ** 24, h=0.01, order=2, tag=40)),
@@ -198,8 +221,14 @@ def leg_small(pm, torch, dev, args, out):
             _, k_nos = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U), 5, 2)
             nbytes = w.samples.size * 8 + N * d * d * (16 if prec == pm.PM_FP64 else 8)
             gbs = nbytes / (k * 1e-3) / 1e9
+            flops = sampled_flops(pm, w, prec)
+            peak = PEAK_FP64_TFLOPS if prec == pm.PM_FP64 else PEAK_FP32_TFLOPS
+            t_roof = max(nbytes / (PEAK_HBM_GBS * 1e9), flops / (peak * 1e12)) * 1e3
             row[name] = {"steps_per_s": N / (wall * 1e-3), "kernel_ms": k, "kernel_ms_without_slices": k_nos,
-                         "algorithmic_bytes": nbytes, "achieved_gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS}
+                         "algorithmic_bytes": nbytes, "achieved_gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS,
+                         "algorithmic_flops": flops, "flop_per_byte": flops / nbytes,
+                         "bound": "hbm" if nbytes / (PEAK_HBM_GBS * 1e9) >= flops / (peak * 1e12) else "mfma",
+                         "roofline_ms": t_roof, "frac_roofline": t_roof / k}
             del sl
             ctx.close()
         res[label] = row

@@ -415,6 +415,34 @@ __device__ __forceinline__ SampleSet<ORD, KB> load_samples(const PropParams& p, 
     return s;
 }
 
+// Midpoint-rule samples of two consecutive slices a, a + 1 with one 16-byte
+// load per control (the pair (j, j + 1), j = min(a, last - 1), lies inside
+// the control's samples): half the load instructions, each lane touching
+// one line per control instead of two.  Slice a takes the first value of
+// the pair unless a >= last, when its sample (a == last) is the second; a
+// slice a + 1 past the end gets some sample and is not used.
+template <int KB>
+__device__ __forceinline__ void load_pair_ord2(const PropParams& p, int64_t a, int64_t last, SampleSet<2, KB>& s0,
+                                               SampleSet<2, KB>& s1) {
+    if (p.K == 0 || last == 0) {
+        s0 = load_samples<2, KB>(p, min(a, last));
+        s1 = s0;
+        return;
+    }
+    const int64_t j = a < last ? a : last - 1;
+    const bool first = a < last;
+    const double* c = p.samples;
+    const int64_t S = p.n_samples;
+#pragma unroll
+    for (int k = 0; k < KB; ++k) {
+        const int kk = min(k, p.K - 1);
+        struct alignas(8) Pair { double x, y; } v;
+        __builtin_memcpy(&v, c + (int64_t)kk * S + j, sizeof(v));
+        s0.v[k] = first ? v.x : v.y;
+        s1.v[k] = v.y;
+    }
+}
+
 // Expand one slice into the upper triangle of G (FP64): the weights of the
 // midpoint rule (order 2) or of eq. magnus_coeffs (order 4, pairs i[H_a,H_b]
 // with a < b in lexicographic order after the 2K single-control terms).
@@ -768,8 +796,12 @@ propagate_valu(PropParams p) {
         }
     };
     auto load_group = [&](SampleSet<ORD, KB> (&dst)[S::R], int64_t i0) {
+        if constexpr (ORD == 2 && S::R == 2) {
+            load_pair_ord2<KB>(p, base + i0, last, dst[0], dst[1]);
+        } else {
 #pragma unroll
-        for (int r = 0; r < S::R; ++r) dst[r] = load_samples<ORD, KB>(p, min(base + i0 + r, last));
+            for (int r = 0; r < S::R; ++r) dst[r] = load_samples<ORD, KB>(p, min(base + i0 + r, last));
+        }
     };
     if constexpr (D == 2) {
         // Samples travel one group ahead in two alternating register sets:
@@ -916,9 +948,11 @@ template <typename T, int D, int ORD>
 hipError_t launch_valu_ord(const PropParams& p, hipStream_t stream) {
     if (p.slices_out && p.du != D) return launch_valu_k<T, D, ORD, kMaxCtrl, OUT_DIRECT>(p, stream);
     if (p.slices_out) {
+        if (p.K <= 1) return launch_valu_k<T, D, ORD, 1, OUT_STAGED>(p, stream);
         if (p.K <= 2) return launch_valu_k<T, D, ORD, 2, OUT_STAGED>(p, stream);
         return launch_valu_k<T, D, ORD, kMaxCtrl, OUT_STAGED>(p, stream);
     }
+    if (p.K <= 1) return launch_valu_k<T, D, ORD, 1, OUT_NONE>(p, stream);
     if (p.K <= 2) return launch_valu_k<T, D, ORD, 2, OUT_NONE>(p, stream);
     return launch_valu_k<T, D, ORD, kMaxCtrl, OUT_NONE>(p, stream);
 }
