@@ -37,7 +37,9 @@ def _time(fn, reps=8, warm=2):
 def tune_propagation(pm, synth, quick):
     import torch
     rows = []
-    classes = [(2, 2 ** 20), (4, 2 ** 19), (16, 2 ** 17), (32, 2 ** 15), (64, 2 ** 13)]
+    # sizes in the throughput regime of each class (the small dimensions are
+    # cheap per slice, so they are tuned on long runs)
+    classes = [(2, 2 ** 24), (4, 2 ** 22), (16, 2 ** 17), (32, 2 ** 15), (64, 2 ** 13)]
     targets = [512, 1024, 2048, 4096, 8192] if not quick else [1024, 2048, 4096]
     for D, N in classes:
         w = synth.random_system(D, 3, n_slices=N, h=1e-3, order=4, tag=D)
@@ -49,7 +51,7 @@ def tune_propagation(pm, synth, quick):
             ctx.set_hamiltonian(w.H0, w.Hk, 4)
             best = None
             for t in targets:
-                unit = 64 if D <= 4 else 1
+                unit = 256 if D <= 4 else 1   # the engines' chunk units
                 chunk = max(unit, unit * math.ceil(N / t / unit))
                 ctx.set_chunk(chunk)
                 ms = _time(lambda: ctx.equiprop_dev(s, w.h, U))

@@ -876,15 +876,27 @@ propagate_valu(PropParams p) {
         }
         W = mat_mul(O, W);
     }
-    // ticketed pairwise tree over the blocks' products (FP64): the node is
-    // published with a release fence before the ticket; only the second
-    // arriver of a pair acquires and reads its sibling
+    // ticketed product tree with fan-in kFanIn over the blocks' products
+    // (FP64): a block publishes its node with a release fence before the
+    // group's ticket; only the group's last arrival acquires, multiplies the
+    // group's nodes (later on the left) and goes on
     const int64_t NN = (int64_t)D * D * 2;
+    auto load_node = [&](int64_t at) {
+        const double* nd = p.nodes + at * NN;
+        Mat<D, double> O;
+#pragma unroll
+        for (int e = 0; e < D * D; ++e) {
+            O.re[e] = nd[2 * e + 0];
+            O.im[e] = nd[2 * e + 1];
+        }
+        return O;
+    };
     int64_t idx = blockIdx.x, cnt = p.n_leaves, off = 0;
     while (cnt > 1) {
-        const int64_t pcnt = (cnt + 1) >> 1, poff = off + cnt, par = idx >> 1;
-        const bool carry = (idx == cnt - 1) && (cnt & 1);
-        if (!carry) {
+        const int64_t pcnt = (cnt + kFanIn - 1) / kFanIn, poff = off + cnt, grp = idx / kFanIn;
+        const int64_t first = grp * kFanIn;
+        const int64_t members = min(cnt, first + kFanIn) - first;
+        if (members > 1) {
             double* node = p.nodes + (off + idx) * NN;
             if (lane == 0) {
 #pragma unroll
@@ -895,21 +907,17 @@ propagate_valu(PropParams p) {
             }
             __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
             unsigned v = 0;
-            if (lane == 0) v = atomicAdd(&p.counters[poff + par], 1u);
+            if (lane == 0) v = atomicAdd(&p.counters[poff + grp], 1u);
             const unsigned t = (unsigned)wave_uniform((int)__shfl(v, 0));
-            if (t == 0) return;
+            if (t != (unsigned)(members - 1)) return;
             __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-            if (lane == 0) atomicExch(&p.counters[poff + par], 0u);
-            const double* sib = p.nodes + (off + (idx ^ 1)) * NN;
-            Mat<D, double> O;
-#pragma unroll
-            for (int e = 0; e < D * D; ++e) {
-                O.re[e] = sib[2 * e + 0];
-                O.im[e] = sib[2 * e + 1];
-            }
-            W = (idx & 1) ? mat_mul(W, O) : mat_mul(O, W);
+            if (lane == 0) atomicExch(&p.counters[poff + grp], 0u);
+            const int64_t lastn = first + members - 1;
+            Mat<D, double> P = lastn == idx ? W : load_node(off + lastn);
+            for (int64_t k = lastn - 1; k >= first; --k) P = mat_mul(P, k == idx ? W : load_node(off + k));
+            W = P;
         }
-        idx = par;
+        idx = grp;
         off = poff;
         cnt = pcnt;
     }
