@@ -47,7 +47,7 @@ PEAK = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "fp32_3m": PEAK_FP32
 # HBM bytes per launch of the headline kernel from the FETCH_SIZE/WRITE_SIZE
 # passes (scaled by a 1 GiB copy: 2.0 x FETCH_SIZE KiB, 1.0 x WRITE_SIZE KiB),
 # valid only while the kernel's sources hash to the value they had then.
-TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_tiles.h", "mfma_tree.h", "engine_common.h", "pm_internal.h"]
+TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_kernel.h", "mfma_tiles.h", "mfma_tree.h", "engine_common.h", "pm_internal.h"]
 MEASURED_TRAFFIC = {"bytes": (2.0 * 4438.671875 + 1.0 * 2360.53125) * 1024.0,
                     "sources_sha256": "e06bc3c2ac43224180a48225262a3e7ea697c29744b26c9b3632561ac1dd2f42",
                     "profile": "profiles/propagate_d16_random_qudit_traffic.md"}

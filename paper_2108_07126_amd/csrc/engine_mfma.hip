@@ -1,239 +1,8 @@
-// MFMA engine for dimensions 16, 32 and 64 (and smaller ones embedded in 16).
-//
-// One *team* of (D/16)^2 wavefronts runs a chain of consecutive slices; each
-// wave owns one 16x16 output tile of every D x D matrix, held in registers in
-// the accumulator layout of v_mfma_*_16x16x4 (lane 16 g + j holds four rows
-// of column j, see crow()).  Per slice the team
-//   1. expands G_j = sum_m w_m B_m in FP64 (lane m gathers the samples of
-//      weight m one slice ahead; basis tiles from LDS or L2 in that layout),
-//   2. bounds ||G_j||_1 and plans the Taylor degree m and squarings s,
-//   3. evaluates exp(-i G) = C(Y) - i G S'(Y), Y = G^2 (cos / sin Taylor
-//      series split by parity: every product is of commuting Hermitian
-//      matrices), then squares s times,
-//   4. optionally stores U_j, and multiplies it into the team's chain
-//      product Q <- U_j Q (later slices on the left, eq. slices).
-// Operands of each complex product are staged in LDS (row stride D+1, split
-// re/im planes, conflict-free fragment reads) and multiplied as four real
-// products on MFMA (FP64: v_mfma_f64_16x16x4f64; FP32: v_mfma_f32_16x16x4f32).
-// Finally the chain products are reduced by a pairwise tree in FP64 whose
-// nodes meet through per-pair tickets: the second team to finish a pair
-// multiplies it (odd leftovers are carried up unchanged) -- the reduction of
-// the Reduction by matrix multiplication section, in one launch.
-#include "mfma_tree.h"
+// MFMA engine: the non-paired instances of the propagation kernel and the
+// dispatch over dimension, precision, method and pairing.
+#include "mfma_kernel.h"
 
 namespace pm {
-namespace {
-
-// Waves per SIMD the register allocation must allow.  D = 16 keeps its
-// whole series in registers; its launch (about two chains per SIMD) never
-// asks for more than two waves per SIMD.
-template <typename T, int D>
-constexpr int min_waves_per_eu() {
-    return D == 16 ? 2 : (D == 64 ? 4 : (std::is_same<T, double>::value ? 3 : 4));
-}
-
-template <typename T, int D, int NT, bool BL, int PMODE, bool CH>
-__global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
-__attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, D>(), 8)))
-propagate_mfma(PropParams p) {
-    using G = Geo<D, NT>;
-    extern __shared__ double dsm[];
-    double* slots = dsm;
-    double* red = slots + NT * 2 * G::SLOT;
-    int* tick = reinterpret_cast<int*>(red + G::TD * D);
-    double* lbasis = red + G::TD * D + 2;
-
-    Lane L;
-    L.lane = threadIdx.x & 63;
-    L.g = L.lane >> 4;
-    L.j = L.lane & 15;
-    const int wave = wave_uniform((int)(threadIdx.x >> 6));
-    const int team = wave / G::TW;
-    L.wt = wave % G::TW;
-    L.TI = L.wt / G::TD;
-    L.TJ = L.wt % G::TD;
-    double* s0 = slots + team * 2 * G::SLOT;
-    double* s1 = s0 + G::SLOT;
-
-    // the block's copy of the basis (same for every slice)
-    if constexpr (BL) {
-        const int n = p.M * G::TW * 512;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
-        __syncthreads();
-    }
-    const double* bas = BL ? lbasis : p.basis;
-
-    // this team's chain of consecutive slices (empty past the end)
-    const int64_t chain = (int64_t)blockIdx.x * NT + team;
-    const int64_t j0 = min(p.n_slices, chain * p.chunk);
-    const int64_t j1 = min(p.n_slices, j0 + p.chunk);
-    constexpr bool kF64 = std::is_same<T, double>::value;
-    // FP64: the chain product in registers.  Reduced modes: slices as I + E
-    // (E accurate relative to ||G||) and the chain as Q <- Q + E Q with Q in
-    // FP64, so the rounding of the working precision never touches the
-    // identity part.
-    Tile<T> Q = ident<T>(L);
-    Tile<double> Qx = ident_as<T>(L);
-    // lane m < M gathers and combines the weight of basis matrix m; the next
-    // slice's samples are loaded while this slice is exponentiated
-    const WeightRecipe wr = weight_recipe(p, L.lane);
-    const double lth = lane_theta_of(p, L.lane);
-    const double lcth = lane_ctheta_of(p, L.lane);
-    SliceSamples smp = gather_samples(p, wr, j0 < j1 ? j0 : 0);
-    for (int64_t j = j0; j < j1; ++j) {
-        const double wl = combine_weight(p, wr, smp);
-        if (j + 1 < j1) smp = gather_samples(p, wr, j + 1);
-        // expand (FP64)
-        double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
-        const int64_t bofs = mfma_basis_index(D, 0, L.TI, L.TJ, 0, 0, L.lane);
-#pragma unroll 4
-        for (int m = 0; m < p.M; ++m) {
-            const double w = readlane_d(wl, m);
-            const double* b = bas + bofs + (int64_t)m * G::TW * 512;
-#pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                gre[r] = fma(w, b[r * 64], gre[r]);
-                gim[r] = fma(w, b[256 + r * 64], gim[r]);
-            }
-        }
-        // plan (FP64)
-        const double nu = wave_uniform(team_norm1<G, T>(gre, gim, L, red));
-        int m, s;
-        if constexpr (CH) plan_cheb_lanes(p, nu, L.lane, lcth, m, s);
-        else plan_expm_lanes(p, nu, L.lane, lth, m, s);
-        m = wave_uniform(m);
-        s = wave_uniform(s);
-        Tile<T> Gt;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            Gt.re[r] = (T)ldexp(gre[r], -s);
-            Gt.im[r] = (T)ldexp(gim[r], -s);
-        }
-        if constexpr (kF64) {
-            // exponentiate, square, store, chain product Q <- U Q
-            Tile<T> U;
-            if constexpr (CH) {
-                U = cheb_exp<G>(Gt, m, p.ctheta[m], p.cheb_j + m * (kMaxCheb + 1), L, s0, s1);
-            } else if constexpr (G::TW == 1) {
-                // one-wave team: the series as the Hermitian pair C - i P and,
-                // without squarings, the chain product straight from it, all
-                // in registers
-                Tile<double> C, P;
-                taylor_parts_reg<double>(Gt, m, L, C, P);
-                if (s == 0) {
-                    if (p.slices_out) store_slice<G, T>(p, j, combine_cp<double>(C, P), L);
-                    Q = reg_mul_cp<double>(C, P, Q);
-                    continue;
-                }
-                U = combine_cp<double>(C, P);
-            } else {
-                U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
-            }
-            if (s > 0) U = square_n<G, double>(U, s, L, s0);
-            if (p.slices_out) store_slice<G, T>(p, j, U, L);
-            team_sync<G>();
-            slot_store<G, T>(s0, U, L);
-            slot_store<G, T>(s1, Q, L);
-            team_sync<G>();
-            Q = mulT<G, T, PMODE>(s0, s1, L);
-        } else {
-            Tile<T> E;
-            if constexpr (G::TW == 1) {
-                // one-wave team: E = C - i P in registers and, without
-                // squarings, Q <- Q + E Q with E Q in registers too
-                Tile<T> C, P;
-                taylor_parts_reg<T, PMODE, true>(Gt, m, L, C, P);
-                if (s == 0) {
-                    if (p.slices_out) store_slice<G, T>(p, j, plus_ident<T>(combine_cp<T>(C, P), L), L);
-                    Tile<T> Qt;
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        Qt.re[r] = (T)Qx.re[r];
-                        Qt.im[r] = (T)Qx.im[r];
-                    }
-                    const Tile<T> EQ = reg_mul_cp<T, PMODE>(C, P, Qt);
-#pragma unroll
-                    for (int r = 0; r < 4; ++r) {
-                        Qx.re[r] += (double)EQ.re[r];
-                        Qx.im[r] += (double)EQ.im[r];
-                    }
-                    continue;
-                }
-                E = combine_cp<T>(C, P);
-            } else {
-                E = taylor_exp<G, T, PMODE, true>(Gt, m, L, s0, s1);
-            }
-            if (s > 0)
-                E = relayout<G, T>(square_excess_n<G>(relayout<G, double>(E, s0, L), s, L, s0), s0, L);
-            if (p.slices_out) store_slice<G, T>(p, j, plus_ident<T>(E, L), L);
-            chain_acc<G, T, PMODE>(Qx, E, L, s0, s1);
-        }
-    }
-    Tile<double> Qd;
-    if constexpr (kF64) Qd = Q;
-    else Qd = relayout_rows<G, T, double>(Qx, s0, L);
-    if (p.chain_out && chain < p.n_chains)
-        node_store<G>(p.chain_out + chain * (int64_t)G::D * G::D * 2, Qd, L);
-    // one-wave teams of a block: combine their chains in LDS (later team on
-    // the left), so the block enters the global tree as a single leaf
-    if constexpr (NT > 1) {
-        for (int st = 1; st < NT; st <<= 1) {
-            __syncthreads();
-            slot_store<G, double>(s1, Qd, L);
-            __syncthreads();
-            if ((team & (2 * st - 1)) == 0) {
-                const double* later = slots + (team + st) * 2 * G::SLOT + G::SLOT;
-                Qd = slot_mul<G, double>(later, s1, L);
-            }
-        }
-        if (team != 0) return;
-    }
-    tree_reduce<G>(p, blockIdx.x, Qd, L, s0, s1, tick);
-}
-
-template <int D, int NT>
-constexpr size_t lds_fixed_bytes() {
-    using G = Geo<D, NT>;
-    return sizeof(double) * ((size_t)NT * 2 * G::SLOT + (size_t)G::TD * D + 2);
-}
-
-template <typename T, int D, int NT, bool BL, int PMODE, bool CH>
-hipError_t launch_one(const PropParams& p, hipStream_t stream) {
-    using G = Geo<D, NT>;
-    const size_t lds = lds_fixed_bytes<D, NT>() + (BL ? sizeof(double) * (size_t)p.M * G::TW * 512 : 0);
-    static bool attr_set = false;
-    if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)propagate_mfma<T, D, NT, BL, PMODE, CH>,
-                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
-        if (e != hipSuccess) return e;
-        attr_set = true;
-    }
-    hipLaunchKernelGGL((propagate_mfma<T, D, NT, BL, PMODE, CH>), dim3((unsigned)p.n_leaves), dim3(G::THREADS), lds,
-                       stream, p);
-    return hipGetLastError();
-}
-
-template <typename T, int D, int NT, int PMODE, bool CH>
-hipError_t launch_bl(const PropParams& p, hipStream_t stream) {
-    if constexpr (D == 16) {
-        if (p.basis_lds) return launch_one<T, D, NT, true, PMODE, CH>(p, stream);
-    }
-    return launch_one<T, D, NT, false, PMODE, CH>(p, stream);
-}
-
-// The Chebyshev series is an FP64 method.
-template <typename T, int D, int NT, int PMODE>
-hipError_t launch_method(const PropParams& p, hipStream_t stream) {
-    if constexpr (std::is_same<T, double>::value) {
-        if (p.method == PM_EXPM_CHEBYSHEV) return launch_bl<T, D, NT, PMODE, true>(p, stream);
-    }
-    return launch_bl<T, D, NT, PMODE, false>(p, stream);
-}
-
-}  // namespace
-
-// Teams per block for the one-wave teams of D = 16.
-constexpr int kNT16 = 4;
 
 template <typename T, int PMODE>
 hipError_t launch_dims(int D, const PropParams& p, hipStream_t stream) {
@@ -245,7 +14,13 @@ hipError_t launch_dims(int D, const PropParams& p, hipStream_t stream) {
     }
 }
 
+hipError_t launch_mfma_pair(int precision, const PropParams& p, hipStream_t stream);
+
 hipError_t launch_mfma(int D, int precision, const PropParams& p, hipStream_t stream) {
+    if (p.pair) {
+        if (D != 16) return hipErrorInvalidValue;
+        return launch_mfma_pair(precision, p, stream);
+    }
     switch (precision) {
         case PM_FP64: return launch_dims<double, 0>(D, p, stream);
         case PM_FP32: return launch_dims<float, 0>(D, p, stream);

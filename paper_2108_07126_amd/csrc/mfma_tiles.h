@@ -709,6 +709,59 @@ __device__ __forceinline__ void store_slice(const PropParams& p, int64_t j, cons
     }
 }
 
+// Per-slice output of a slice pair (one-wave 16-wide tile, d <= 8): the
+// upper-left block holds slice ja, the lower-right one slice jb (none when
+// jb < 0).
+template <class G, typename T>
+__device__ __forceinline__ void store_slice_pair(const PropParams& p, int64_t ja, int64_t jb, const Tile<T>& U,
+                                                 const Lane& L) {
+    const int du = p.du;
+    const bool second = L.j >= 8;
+    const int64_t js = second ? jb : ja;
+    const int col = second ? L.j - 8 : L.j;
+    if (js < 0 || col >= du) return;
+    T* out = reinterpret_cast<T*>(p.slices_out) + js * (int64_t)du * du * 2;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = crow<T>(L.g, r);
+        const int rb = second ? row - 8 : row;
+        if ((second ? row >= 8 : row < 8) && rb < du) {
+            out[(rb * du + col) * 2 + 0] = U.re[r];
+            out[(rb * du + col) * 2 + 1] = U.im[r];
+        }
+    }
+}
+
+// The chain product of a slice-pair team: from Q = Q_A (+) Q_B (the two
+// halves' products in the diagonal blocks), Q_B Q_A in the upper-left block
+// with the identity elsewhere, the layout of an unpaired chain product.
+template <class G>
+__device__ __forceinline__ Tile<double> pair_product(const Tile<double>& Q, const Lane& L, double* s0, double* s1) {
+    static_assert(G::D == 16 && G::TW == 1, "slice pairs live in one-wave 16-wide tiles");
+    team_sync<G>();
+    slot_store<G, double>(s0, Q, L);
+    team_sync<G>();
+    const double* re = s0;
+    const double* im = s0 + G::PLANE;
+    Tile<double> X, Y;
+    const int col = L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = crow<double>(L.g, r);
+        const bool in = row < 8 && col < 8;
+        const double id = row == col ? 1.0 : 0.0;
+        X.re[r] = in ? re[(row + 8) * G::LD + col + 8] : id;
+        X.im[r] = in ? im[(row + 8) * G::LD + col + 8] : 0.0;
+        Y.re[r] = in ? re[row * G::LD + col] : id;
+        Y.im[r] = in ? im[row * G::LD + col] : 0.0;
+    }
+    team_sync<G>();
+    slot_store<G, double>(s0, X, L);
+    slot_store<G, double>(s1, Y, L);
+    team_sync<G>();
+    return slot_mul<G, double>(s0, s1, L);
+}
+
 template <class G>
 __device__ __forceinline__ void node_store(double* node, const Tile<double>& t, const Lane& L) {
     const int col = 16 * L.TJ + L.j;

@@ -53,6 +53,7 @@ struct pm_ctx {
     size_t nodes_bytes = 0;
     unsigned* d_counters = nullptr;
     size_t counters_bytes = 0;
+    double* d_basis_pair = nullptr;   // D = 16, d <= 8: the basis in both diagonal blocks
     double* d_samples = nullptr;
     size_t samples_bytes = 0;
     double* d_U = nullptr;
@@ -489,6 +490,12 @@ pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, bool keep_nodes, const d
     // D = 16: the block keeps the basis in LDS when it is small (<= 64 KiB)
     p.basis_lds = (e.kind == pm::ENGINE_MFMA && e.D == 16 &&
                    (size_t)ctx->M * e.D * e.D * 16 <= 64 * 1024) ? 1 : 0;
+    // two slices per tile for plain Taylor propagations of dimension <= 8
+    if (!keep_nodes && ctx->d_basis_pair && basis == ctx->d_basis && ctx->method == PM_EXPM_TAYLOR &&
+        e.kind == pm::ENGINE_MFMA && e.D == 16) {
+        p.pair = 1;
+        p.basis = ctx->d_basis_pair;
+    }
     std::memcpy(p.pair_a, ctx->pair_a, sizeof(p.pair_a));
     std::memcpy(p.pair_b, ctx->pair_b, sizeof(p.pair_b));
     return PM_OK;
@@ -762,6 +769,7 @@ pm_status pm_destroy(pm_ctx* ctx) {
         dfree(ctx->d_samples);
         dfree(ctx->d_U);
         dfree(ctx->d_basis_grad);
+        dfree(ctx->d_basis_pair);
         dfree(ctx->d_cheb);
         dfree(ctx->d_mom);
         dfree(ctx->d_chain);
@@ -896,6 +904,31 @@ pm_status pm_set_hamiltonian(pm_ctx* ctx, int64_t dim, const double* H0, int64_t
             he = hipMemcpy(ctx->d_basis_grad, glay.data(), glay.size() * sizeof(double), hipMemcpyHostToDevice);
             if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy gradient basis");
         }
+    }
+    // slice pairs: the basis in both diagonal 8 x 8 blocks of the 16-wide
+    // tile, for dimensions <= 8 and at most 32 basis matrices
+    dfree(ctx->d_basis_pair);
+    if (e.kind == pm::ENGINE_MFMA && e.D == 16 && dim <= 8 && M <= 32) {
+        std::vector<double> dual((size_t)M * 16 * 16 * 2, 0.0);
+        for (int m = 0; m < M; ++m)
+            for (int64_t r = 0; r < dim; ++r)
+                for (int64_t c = 0; c < dim; ++c)
+                    for (int half = 0; half < 2; ++half) {
+                        const size_t at = (((size_t)m * 16 + r + 8 * half) * 16 + c + 8 * half) * 2;
+                        dual[at + 0] = flat[((size_t)m * dim * dim + r * dim + c) * 2 + 0];
+                        dual[at + 1] = flat[((size_t)m * dim * dim + r * dim + c) * 2 + 1];
+                    }
+        std::vector<double> play((size_t)pm::basis_layout_doubles(e, M));
+        pm::basis_to_layout(e, M, 16, dual.data(), play.data());
+        he = hipMalloc((void**)&ctx->d_basis_pair, play.size() * sizeof(double));
+        if (he != hipSuccess) {
+            ctx->d_basis_pair = nullptr;
+            (void)hipGetLastError();
+            ctx->ready = false;
+            return fail(ctx, PM_E_OOM, "hipMalloc failed for the slice-pair basis");
+        }
+        he = hipMemcpy(ctx->d_basis_pair, play.data(), play.size() * sizeof(double), hipMemcpyHostToDevice);
+        if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpy slice-pair basis");
     }
     ctx->dim = dim;
     ctx->n_ctrl = n_ctrl;

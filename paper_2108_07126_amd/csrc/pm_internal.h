@@ -38,6 +38,7 @@ struct PropParams {
     int K, M, order, du;
     int max_degree, force_s;
     int basis_lds;               // MFMA engine: block keeps a copy of the basis in LDS
+    int pair;                    // MFMA engine, D = 16: two slices of dimension <= 8 per tile
     int method;                  // PM_EXPM_TAYLOR or PM_EXPM_CHEBYSHEV
     const double* cheb_j;        // Chebyshev: [m][k] = J_k(ctheta[m]), k <= m <= kMaxCheb
     double ctheta[kMaxCheb + 1]; // Chebyshev: half-width of the spectral interval for degree m

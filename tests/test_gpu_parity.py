@@ -160,6 +160,18 @@ def test_chunking_and_tree_shape_invariance(pm, d):
     assert np.array_equal(again, ref)
 
 
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_small_dims_deep_tree(pm, d):
+    """The small-dimension engine with about 150 leaves (three levels of the
+    fan-in-8 tree, a ragged last group and a ragged last chain) against the
+    oracle, and against a shallower split of the same slices."""
+    w = synth.random_system(d, 2, n_slices=150_001, h=0.01, order=2, tag=70 + d)
+    Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 2)
+    U = run(pm, w, chunk=256)
+    assert orc.relative_frobenius(U, Uo) <= TOL64
+    assert orc.relative_frobenius(run(pm, w, chunk=8192), U) <= 1e-12
+
+
 def test_state_machine_and_errors(pm):
     with pm.Context() as ctx:
         with pytest.raises(pm.ParamentError) as e:
