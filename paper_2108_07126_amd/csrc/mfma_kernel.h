@@ -110,18 +110,46 @@ propagate_mfma(PropParams p) {
         // expand (FP64)
         double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
         const int64_t bofs = mfma_basis_index(D, 0, L.TI, L.TJ, 0, 0, L.lane);
-#pragma unroll 4
-        for (int m = 0; m < p.M; ++m) {
-            double w = readlane_d(wl, m);
-            if constexpr (PAIR) {
-                const double w2 = readlane_d(wl, 32 + m);
-                w = bsecond ? w2 : w;
-            }
-            const double* b = bas + bofs + (int64_t)m * G::TW * 512;
+        {
+            // four basis matrices' entries are loaded before their FMAs, so
+            // the load latencies overlap; the sum still runs in order of m
+            const double* bb = bas + bofs;
+            constexpr int64_t STR = G::TW * 512;
+            int m = 0;
+            for (; m + 4 <= p.M; m += 4) {
+                double x[4][8];
 #pragma unroll
-            for (int r = 0; r < 4; ++r) {
-                gre[r] = fma(w, b[r * 64], gre[r]);
-                gim[r] = fma(w, b[256 + r * 64], gim[r]);
+                for (int q = 0; q < 4; ++q)
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        x[q][r] = bb[(m + q) * STR + r * 64];
+                        x[q][4 + r] = bb[(m + q) * STR + 256 + r * 64];
+                    }
+#pragma unroll
+                for (int q = 0; q < 4; ++q) {
+                    double w = readlane_d(wl, m + q);
+                    if constexpr (PAIR) {
+                        const double w2 = readlane_d(wl, 32 + m + q);
+                        w = bsecond ? w2 : w;
+                    }
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) {
+                        gre[r] = fma(w, x[q][r], gre[r]);
+                        gim[r] = fma(w, x[q][4 + r], gim[r]);
+                    }
+                }
+            }
+            for (; m < p.M; ++m) {
+                double w = readlane_d(wl, m);
+                if constexpr (PAIR) {
+                    const double w2 = readlane_d(wl, 32 + m);
+                    w = bsecond ? w2 : w;
+                }
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    gre[r] = fma(w, bb[m * STR + r * 64], gre[r]);
+                    gim[r] = fma(w, bb[m * STR + 256 + r * 64], gim[r]);
+                }
             }
         }
         // plan (FP64)
