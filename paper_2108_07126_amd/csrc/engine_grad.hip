@@ -463,9 +463,24 @@ trajectory_mfma(TrajParams tp) {
             Gt.re[r] = ldexp(gre[r], -s);
             Gt.im[r] = ldexp(gim[r], -s);
         }
-        const Tile<double> U = square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
-        S = mul2<G>(U, S, L, s0, s1);
-        if (tp.kind == PM_TRAJ_DENSITY) S = mul_adjB<G>(S, U, L, s0, s1);
+        if constexpr (G::TW == 1) {
+            // one-wave team: the series as the Hermitian pair C - i P in
+            // registers; without squarings U S straight from it (the density
+            // kind's S U^H has a non-Hermitian left factor and is staged)
+            Tile<double> C, P;
+            taylor_parts_reg<double>(Gt, m, L, C, P);
+            if (s == 0 && tp.kind != PM_TRAJ_DENSITY) {
+                S = reg_mul_cp<double>(C, P, S);
+                continue;
+            }
+            const Tile<double> U = square_n<G, double>(combine_cp<double>(C, P), s, L, s0);
+            S = mul2<G>(U, S, L, s0, s1);
+            if (tp.kind == PM_TRAJ_DENSITY) S = mul_adjB<G>(S, U, L, s0, s1);
+        } else {
+            const Tile<double> U = square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
+            S = mul2<G>(U, S, L, s0, s1);
+            if (tp.kind == PM_TRAJ_DENSITY) S = mul_adjB<G>(S, U, L, s0, s1);
+        }
     }
     if (j1 == p.n_slices) store_block<G>(tp.out + (p.n_slices >> vs) * stride, S, du, cols, cols, L);
 }
