@@ -175,6 +175,41 @@ def leg_d64(pm, torch, dev, args, out):
     return w, Ug
 
 
+def batch_flops(pm, ws, precision, sample: int = 128) -> float:
+    """Algorithmic flops of a batch at each instance's own dimension d:
+    per slice 8 d^3 per complex product (Taylor products, squarings, chain)
+    plus 4 M d^2 for the expand, the planner's (m, s) on `sample` evenly
+    spaced slices of each instance scaled to its N (orders 2 and 4)."""
+    total = 0.0
+    for w in ws:
+        B, _ = pm.build_basis_host(w.H0, w.Hk, w.order)
+        M, d, n, K, h = B.shape[0], w.dim, w.n_slices, w.n_ctrl, w.h
+        idx = np.unique(np.linspace(0, n - 1, min(n, sample)).astype(np.int64))
+        Wt = np.zeros((idx.size, M))
+        Wt[:, 0] = h
+        S = w.samples
+        if K:
+            if w.order == 2:
+                Wt[:, 1:1 + K] = h * S[:, idx].T
+            else:
+                s0, s1, s2 = S[:, 2 * idx], S[:, 2 * idx + 1], S[:, 2 * idx + 2]
+                Wt[:, 1:1 + K] = (h / 6) * (s0 + 4 * s1 + s2).T
+                Wt[:, 1 + K:1 + 2 * K] = (h * h / 12) * (s2 - s0).T
+                q = 1 + 2 * K
+                for a in range(K):
+                    for b in range(a + 1, K):
+                        Wt[:, q] = (h * h / 12) * (s0[a] * s2[b] - s2[a] * s0[b])
+                        q += 1
+        G = np.tensordot(Wt, B, axes=1)
+        nu = np.max(np.sum(np.abs(G), axis=1), axis=1)
+        prods = 0
+        for x in nu:
+            m, s_ = pm.plan_expm(float(x), precision, n_slices=n)
+            prods += taylor_products(m) + s_ + 1
+        total += (8.0 * d ** 3 * prods + 4.0 * M * d * d * idx.size) * (n / idx.size)
+    return total
+
+
 def sampled_flops(pm, w, precision, sample: int = 65536) -> float:
     """Algorithmic flops of a propagation at the user dimension d: per slice
     8 d^3 per complex product (Taylor products, squarings, chain) plus
@@ -468,9 +503,12 @@ def main():
         bt.set(ws)
         t_set = time.perf_counter() - t0
         wall_b, k_b = time_launches(lambda: bt.run(torch.cuda.current_stream()), 3, 1)
+        fl = batch_flops(pm, ws, pm.PM_FP32_3M)
         out["batch"] = {"workload": "512 uneven instances (d 2..64, K 1..4, N 1e3..1e5, orders 2/4)",
                         "precision": "fp32_3m", "slices": nsl, "packets": bt.n_packets, "ms_per_run": wall_b,
-                        "kernel_ms": k_b, "steps_per_s": nsl / (wall_b * 1e-3), "set_s": t_set}
+                        "kernel_ms": k_b, "steps_per_s": nsl / (wall_b * 1e-3), "set_s": t_set,
+                        "algorithmic_flops": fl, "achieved_tflops": fl / (k_b * 1e-3) / 1e12,
+                        "frac_fp32_peak": fl / (k_b * 1e-3) / 1e12 / PEAK_FP32_TFLOPS}
         bt.close()
 
     Uo = None
