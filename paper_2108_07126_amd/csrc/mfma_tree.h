@@ -83,16 +83,40 @@ __device__ void tree_reduce_groups(const PropParams& p, int64_t leaf, Tile<doubl
             if (t != (unsigned)(members - 1)) return;
             if (active && L.lane == 0 && L.wt == 0) atomicExch(&p.counters[poff + grp], 0u);
             const int64_t last = first + members - 1;
-            Tile<double> P = (last == idx || !active) ? Q : node_load<G>(p.nodes + (off + last) * NN, L);
-            for (int64_t k = last - 1; k >= first; --k) {
-                const Tile<double> X = (k == idx || !active) ? Q : node_load<G>(p.nodes + (off + k) * NN, L);
-                team_sync<G>();
-                slot_store<G, double>(s0, P, L);   // left factor: later slices
-                slot_store<G, double>(s1, X, L);
-                team_sync<G>();
-                P = slot_mul<G, double>(s0, s1, L);
+            if constexpr (G::TW == 1) {
+                // one-wave team (its chain registers are free by now): the
+                // group's nodes are loaded together, so their latencies
+                // after the acquire overlap instead of adding up
+                Tile<double> X[kFanIn];
+#pragma unroll
+                for (int q = 0; q < kFanIn; ++q)
+                    X[q] = (q < members && first + q != idx) ? node_load<G>(p.nodes + (off + first + q) * NN, L) : Q;
+                Tile<double> P = Q;
+#pragma unroll
+                for (int q = 0; q < kFanIn; ++q)
+                    if (q == members - 1) P = X[q];
+#pragma unroll
+                for (int q = kFanIn - 2; q >= 0; --q)
+                    if (q <= members - 2) {
+                        team_sync<G>();
+                        slot_store<G, double>(s0, P, L);   // left factor: later slices
+                        slot_store<G, double>(s1, X[q], L);
+                        team_sync<G>();
+                        P = slot_mul<G, double>(s0, s1, L);
+                    }
+                Q = P;
+            } else {
+                Tile<double> P = (last == idx || !active) ? Q : node_load<G>(p.nodes + (off + last) * NN, L);
+                for (int64_t k = last - 1; k >= first; --k) {
+                    const Tile<double> X = (k == idx || !active) ? Q : node_load<G>(p.nodes + (off + k) * NN, L);
+                    team_sync<G>();
+                    slot_store<G, double>(s0, P, L);   // left factor: later slices
+                    slot_store<G, double>(s1, X, L);
+                    team_sync<G>();
+                    P = slot_mul<G, double>(s0, s1, L);
+                }
+                Q = P;
             }
-            Q = P;
         }
         idx = grp;
         off = poff;
