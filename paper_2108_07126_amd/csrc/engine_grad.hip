@@ -244,8 +244,19 @@ __device__ Tile<double> chain_checkpoint(const PropParams& p, int64_t chain, con
             cnt = (cnt + kFanIn - 1) / kFanIn;
         }
         const int64_t first = (b >> (kFanInLog2 * (l + 1))) << kFanInLog2;
-        for (int64_t k = 0; k < d; ++k)
-            P = mul2<G>(node_load<G>(p.nodes + (off + first + k) * NN, L), P, L, s0, s1);
+        if constexpr (G::TW == 1) {
+            // one-wave team: the level's nodes are loaded together
+            Tile<double> X[kFanIn - 1];
+#pragma unroll
+            for (int q = 0; q < kFanIn - 1; ++q)
+                if (q < d) X[q] = node_load<G>(p.nodes + (off + first + q) * NN, L);
+#pragma unroll
+            for (int q = 0; q < kFanIn - 1; ++q)
+                if (q < d) P = mul2<G>(X[q], P, L, s0, s1);
+        } else {
+            for (int64_t k = 0; k < d; ++k)
+                P = mul2<G>(node_load<G>(p.nodes + (off + first + k) * NN, L), P, L, s0, s1);
+        }
     }
     for (int64_t c = b * G::NT; c < chain; ++c)
         P = mul2<G>(node_load<G>(p.chain_out + c * NN, L), P, L, s0, s1);
