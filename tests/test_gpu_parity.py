@@ -160,6 +160,19 @@ def test_chunking_and_tree_shape_invariance(pm, d):
     assert np.array_equal(again, ref)
 
 
+@pytest.mark.parametrize("d", [2, 4, 5, 8, 16, 32, 64])
+def test_largest_basis_order4(pm, d):
+    """Eight controls with 4th-order Magnus: 45 basis matrices (the largest
+    basis; past the LDS copy on the MFMA engines, the last commutator pairs
+    in the weight recipe), FP64 and FP32-3M against the oracle."""
+    n = 60 if d == 64 else 200
+    w = synth.random_system(d, 8, n_slices=n, h=0.02, order=4, tag=90 + d)
+    Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 4)
+    assert orc.relative_frobenius(run(pm, w), Uo) <= TOL64, d
+    e = orc.relative_frobenius(run(pm, w, precision=pm.PM_FP32_3M), Uo)
+    assert e <= 2 * tol32(n, d), (d, e)
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 4])
 def test_small_dims_deep_tree(pm, d):
     """The small-dimension engine with about 150 leaves (three levels of the
