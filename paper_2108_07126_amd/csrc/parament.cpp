@@ -490,8 +490,10 @@ pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, bool keep_nodes, const d
     // D = 16: the block keeps the basis in LDS when it is small (<= 64 KiB)
     p.basis_lds = (e.kind == pm::ENGINE_MFMA && e.D == 16 &&
                    (size_t)ctx->M * e.D * e.D * 16 <= 64 * 1024) ? 1 : 0;
-    // two slices per tile for plain Taylor propagations of dimension <= 8
-    if (!keep_nodes && ctx->d_basis_pair && basis == ctx->d_basis && ctx->method == PM_EXPM_TAYLOR &&
+    // two slices per tile for Taylor propagations of dimension <= 8 (also
+    // the checkpointed forward pass: its chain products and tree nodes come
+    // out in the unpaired layout)
+    if (ctx->d_basis_pair && basis == ctx->d_basis && (ctx->method == PM_EXPM_TAYLOR || keep_nodes) &&
         e.kind == pm::ENGINE_MFMA && e.D == 16) {
         p.pair = 1;
         p.basis = ctx->d_basis_pair;
@@ -534,6 +536,9 @@ pm_status forward_keep(pm_ctx* ctx, const double* d_samples, int64_t n_samples, 
         const hipError_t he = pm::launch_propagate(e, PM_FP64, p, stream);
         if (he != hipSuccess) return hip_fail(ctx, he, "forward launch");
     }
+    // the backward and trajectory kernels recompute single slices
+    p.pair = 0;
+    p.basis = basis;
     return PM_OK;
 }
 
