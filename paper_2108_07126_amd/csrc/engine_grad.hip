@@ -291,31 +291,28 @@ backward_mfma(GradParams gp) {
         __syncthreads();
     }
     const double* bas = BL ? lbasis : p.basis;
-    const int64_t chain = (int64_t)blockIdx.x * NT + team;
+    // backward unit: part `part` of chain `chain` (split parts of equal length)
+    const int64_t unit = (int64_t)blockIdx.x * NT + team;
+    const int64_t chain = unit / gp.split;
+    const int64_t part = unit % gp.split;
     if (chain >= p.n_chains) return;   // no block-wide barrier follows
-    const int64_t j0 = chain * p.chunk;
-    const int64_t j1 = min(p.n_slices, j0 + p.chunk);
-
-    // checkpoint P = U_{j0-1} ... U_0
-    const Tile<double> P = chain_checkpoint<G>(p, chain, L, s0, s1);
-    // Omega_{j0} = P Z P^H, Z = W^H U(T)
-    const Tile<double> Wt = load_user<G>(gp.W, p.du, 0.0, L);
-    const Tile<double> UTt = load_user<G>(gp.UT, p.du, 1.0, L);
-    const Tile<double> Z = mul_adjA<G>(Wt, UTt, L, s0, s1);
-    Tile<double> Om = mul_adjB<G>(mul2<G>(P, Z, L, s0, s1), P, L, s0, s1);
+    const int64_t c0 = chain * p.chunk, c1 = min(p.n_slices, c0 + p.chunk);
+    const int64_t sub = (p.chunk + gp.split - 1) / gp.split;
+    const int64_t j0 = min(c1, c0 + part * sub);
+    const int64_t j1 = min(c1, j0 + sub);
+    if (j0 >= j1) return;
 
     const WeightRecipe wr = weight_recipe(p, L.lane);
     const double lth = lane_theta_of(p, L.lane);
-    SliceSamples smp = gather_samples(p, wr, j0);
     const int64_t bofs = mfma_basis_index(D, 0, L.TI, L.TJ, 0, 0, L.lane);
-    for (int64_t j = j0; j < j1; ++j) {
+    // slice j's exponent, scaled by 2^-s for its plan (m, s)
+    auto slice_exponent = [&](const SliceSamples& smp, Tile<double>& Gt, int& m, int& s) {
         const double wl = combine_weight(p, wr, smp);
-        if (j + 1 < j1) smp = gather_samples(p, wr, j + 1);
         double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
 #pragma unroll 4
-        for (int m = 0; m < p.M; ++m) {
-            const double w = readlane_d(wl, m);
-            const double* bb = bas + bofs + (int64_t)m * G::TW * 512;
+        for (int mm = 0; mm < p.M; ++mm) {
+            const double w = readlane_d(wl, mm);
+            const double* bb = bas + bofs + (int64_t)mm * G::TW * 512;
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 gre[r] = fma(w, bb[r * 64], gre[r]);
@@ -323,16 +320,39 @@ backward_mfma(GradParams gp) {
             }
         }
         const double nu = wave_uniform(team_norm1<G, double>(gre, gim, L, red));
-        int m, s;
         plan_expm_lanes(p, nu, L.lane, lth, m, s);
         m = wave_uniform(m);
         s = wave_uniform(s);
-        Tile<double> Gt;
 #pragma unroll
         for (int r = 0; r < 4; ++r) {
             Gt.re[r] = ldexp(gre[r], -s);
             Gt.im[r] = ldexp(gim[r], -s);
         }
+    };
+
+    // checkpoint P = U_{j0-1} ... U_0: the chain's, then the unit's
+    // predecessors in the chain recomputed
+    Tile<double> P = chain_checkpoint<G>(p, chain, L, s0, s1);
+    for (int64_t j = c0; j < j0; ++j) {
+        Tile<double> Gt;
+        int m, s;
+        slice_exponent(gather_samples(p, wr, j), Gt, m, s);
+        const Tile<double> U = square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
+        P = mul2<G>(U, P, L, s0, s1);
+    }
+    // Omega_{j0} = P Z P^H, Z = W^H U(T)
+    const Tile<double> Wt = load_user<G>(gp.W, p.du, 0.0, L);
+    const Tile<double> UTt = load_user<G>(gp.UT, p.du, 1.0, L);
+    const Tile<double> Z = mul_adjA<G>(Wt, UTt, L, s0, s1);
+    Tile<double> Om = mul_adjB<G>(mul2<G>(P, Z, L, s0, s1), P, L, s0, s1);
+
+    SliceSamples smp = gather_samples(p, wr, j0);
+    for (int64_t j = j0; j < j1; ++j) {
+        const SliceSamples cur = smp;
+        if (j + 1 < j1) smp = gather_samples(p, wr, j + 1);
+        Tile<double> Gt;
+        int m, s;
+        slice_exponent(cur, Gt, m, s);
         // U_j and Lambda_j = Omega_j U_j^H
         Tile<double> U = square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
         const Tile<double> Lam = mul_adjB<G>(Om, U, L, s0, s1);
@@ -566,7 +586,7 @@ hipError_t launch_bwd(const GradParams& gp, size_t lds, hipStream_t stream) {
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    const int64_t blocks = (gp.p.n_chains + NT - 1) / NT;
+    const int64_t blocks = (gp.p.n_chains * gp.split + NT - 1) / NT;
     hipLaunchKernelGGL((backward_mfma<D, NT, BL>), dim3((unsigned)blocks), dim3(64 * (D / 16) * (D / 16) * NT),
                        lds, stream, gp);
     return hipGetLastError();

@@ -559,6 +559,11 @@ pm_status launch_grad(pm_ctx* ctx, const double* d_samples, int64_t n_samples, d
     gp.W = d_W;
     gp.UT = ctx->d_UT;
     gp.gw = ctx->d_gw;
+    // few long chains: split each into parts of at least four slices (each
+    // part recomputes its predecessors in the chain) until about 2048 units
+    // run; shorter parts lose more to the recomputation than they gain
+    gp.split = 1;
+    while (p.n_chains * gp.split * 2 <= 2048 && p.chunk >= 8 * gp.split) gp.split *= 2;
     he = pm::launch_backward(e.D, gp, d_grad, stream);
     if (he != hipSuccess) return hip_fail(ctx, he, "backward launch");
     return PM_OK;

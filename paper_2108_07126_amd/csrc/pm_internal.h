@@ -52,6 +52,7 @@ struct GradParams {
     const double* W;    // [du][du] complex128, dL = Re Tr(W^H dU(T))
     const double* UT;   // [du][du] complex128, U(T) of that forward
     double* gw;         // [N][M] dL / d w_{j,m}
+    int split;          // backward units per chain (>= 1): unit u covers part u % split of chain u / split
 };
 
 // Trajectory kernel arguments (PM_TRAJ_* kinds of the public header).
