@@ -123,6 +123,24 @@ def test_gradient_matches_oracle(pm, d):
         assert err <= 1e-9, (d, n, err)
 
 
+@pytest.mark.parametrize("d", [8, 16])
+def test_gradient_split_chains(pm, d):
+    """Chains of 10 and 14 exponentials are split into backward parts of 5
+    and 7: parts that start on the second factor of a slice."""
+    w = synth.random_system(d, 2, n_slices=37, h=0.09, order=CF4, tag=345)
+    V = synth.haar_unitary(np.random.default_rng(d + 99), d)
+    U = orc.propagate(w.H0, w.Hk, w.samples, w.h, CF4)
+    _, go = orc.control_gradient(w.H0, w.Hk, w.samples, w.h, CF4, orc.fidelity_grad_U(U, V))
+    for chunk in (10, 14):
+        say(f"[case] cf4 grad split d={d} chunk={chunk}")
+        with pm.Context() as ctx:
+            ctx.set_hamiltonian(w.H0, w.Hk, CF4)
+            ctx.set_chunk(chunk)
+            _, gg, _ = ctx.fidelity_grad(w.samples, w.h, V)
+        err = float(np.max(np.abs(gg - go)) / np.max(np.abs(go)))
+        assert err <= 1e-9, (d, chunk, err)
+
+
 @pytest.mark.parametrize("d", [2, 5, 16, 32])
 def test_trajectory_matches_oracle(pm, d):
     for n, chunk in ((1, 0), (40, 0), (203, 5)):

@@ -118,6 +118,41 @@ def test_grad_checkpoint_interval_invariance(pm):
     assert np.array_equal(g2, g0)
 
 
+def test_contexts_on_concurrent_streams(pm):
+    """Eight independent evaluations enqueued at once on four contexts with
+    four streams: each equals its context's result when run alone."""
+    import torch
+    ws = [synth.qubit_register(n_slices=500, tag=1100 + i) for i in range(8)]
+    say("[case] grad 8 evaluations on 4 streams")
+    ctxs = [pm.Context() for _ in range(4)]
+    try:
+        for c in ctxs:
+            c.set_hamiltonian(ws[0].H0, ws[0].Hk, 2)
+        S = [torch.tensor(w.samples, device="cuda") for w in ws]
+        W = [torch.tensor(-(2.0 / 64) * w.target, device="cuda") for w in ws]
+        G = [torch.zeros_like(s) for s in S]
+        alone = []
+        for i, w in enumerate(ws):
+            ctxs[i % 4].backward_dev(S[i], w.h, W[i], G[i])
+            torch.cuda.synchronize()
+            alone.append(G[i].cpu().numpy())
+            G[i].zero_()
+        torch.cuda.synchronize()
+        streams = [torch.cuda.Stream() for _ in range(4)]
+        for i, w in enumerate(ws):
+            ctxs[i % 4].backward_dev(S[i], w.h, W[i], G[i], stream=streams[i % 4])
+        torch.cuda.synchronize()
+        for i in range(8):
+            assert np.array_equal(G[i].cpu().numpy(), alone[i]), i
+        # and the first against the oracle (W = dL/dU-bar of Re Tr(W^H U))
+        U = orc.propagate(ws[0].H0, ws[0].Hk, ws[0].samples, ws[0].h, 2)
+        _, go = orc.control_gradient(ws[0].H0, ws[0].Hk, ws[0].samples, ws[0].h, 2, -(2.0 / 64) * ws[0].target)
+        assert rel(alone[0], go) <= TOL
+    finally:
+        for c in ctxs:
+            c.close()
+
+
 def test_autograd_function(pm):
     import torch
     w = synth.random_system(8, 2, n_slices=300, h=0.04, order=4, tag=21)
