@@ -290,11 +290,14 @@ pm_status pm_set_chunk(pm_ctx *ctx, int64_t chunk);
  * otherwise); the gradient entry points always use the Taylor series. */
 pm_status pm_set_expm_method(pm_ctx *ctx, int method);
 
-/* The decomposition a propagation of n_samples samples would use on this
- * context (after pm_set_hamiltonian; host-only, nothing is launched):
- * *chunk slices per chain, *chains chains, *leaves leaves of the pairwise
- * tree (chains are combined per block before the tree, so leaves <= chains).
- * The reduction performs chains - 1 products after the chains. */
+/* The decomposition a propagation of n_samples samples that returns U(T)
+ * only would use on this context (after pm_set_hamiltonian; host-only,
+ * nothing is launched): *chunk slices per chain, *chains chains, *leaves
+ * leaves of the product tree (chains are combined per block before the tree,
+ * so leaves <= chains).  The reduction performs chains - 1 products after the
+ * chains.  Without a pm_set_chunk override, a propagation with per-slice
+ * output on dimensions 1 and 2 uses one chain per resident wave instead of the
+ * tuned count. */
 pm_status pm_launch_shape(pm_ctx *ctx, int64_t n_samples, int64_t *chunk, int64_t *chains,
                           int64_t *leaves);
 

@@ -408,11 +408,16 @@ int tune_class(int D) {
 }
 
 // Chain length: about one chain per resident wave team (or the tuned count),
-// in whole units.
-int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool keep_nodes) {
+// in whole units.  The tuned counts are measured on propagations that return
+// U(T) only; with per-slice output the two-dimensional VALU kernel keeps one
+// chain per resident wave (two per SIMD): in FP32 at 2^26 slices 1.14 ms
+// against 1.38 ms with the tuned 1024 chains (FP64 is tuned to the same count;
+// for d=4 the tuned counts measured as fast or faster).
+int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool keep_nodes, bool per_slice) {
     int64_t target = (int64_t)e.resident_chains;
     const int tc = tune_class(e.D);
-    if (tc >= 0 && precision >= 0 && precision < 4 && g_tune_chains[tc][precision] > 0)
+    const bool tuned = !(per_slice && e.kind == pm::ENGINE_VALU && e.D == 2);
+    if (tuned && tc >= 0 && precision >= 0 && precision < 4 && g_tune_chains[tc][precision] > 0)
         target = g_tune_chains[tc][precision];
     int64_t c = (N + target - 1) / target;
     if (c < 1) c = 1;
@@ -431,8 +436,10 @@ int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool keep_
 // Chain length of a propagation: the user's, else the automatic one; whole
 // units, and for the VALU engine at most 2^20 slices (its per-slice output
 // addresses a chain's slices with 32-bit offsets).
-int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, bool keep_nodes = false) {
-    int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override : auto_chunk(e, N, ctx->precision, keep_nodes);
+int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, bool keep_nodes = false,
+                        bool per_slice = false) {
+    int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override
+                                        : auto_chunk(e, N, ctx->precision, keep_nodes, per_slice);
     c = ((c + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
     if (e.kind == pm::ENGINE_VALU && c > (int64_t(1) << 20)) c = int64_t(1) << 20;
     // CF4: a chain starts at a slice boundary (an even exponential index)
@@ -444,7 +451,7 @@ int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, b
 pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, bool keep_nodes, const double* basis, const double* d_samples,
                   int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out) {
     const int64_t N = n_exps_of(ctx->order, n_samples);
-    const int64_t chunk = effective_chunk(ctx, e, N, keep_nodes);
+    const int64_t chunk = effective_chunk(ctx, e, N, keep_nodes, d_slices != nullptr);
     const int64_t chains = (N + chunk - 1) / chunk;
     const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
     const size_t node_bytes = (size_t)e.D * e.D * 16;
