@@ -14,7 +14,7 @@
  *   2. exponentiate all slices at once, U_j = exp(-i G_j), by scaling and
  *      squaring with a truncated Taylor series (Matrix exponential section);
  *   3. reduce U(T) = U_{N-1} ... U_1 U_0 (eq. slices) by chunked products and
- *      a log-depth pairwise tree (Reduction by matrix multiplication section).
+ *      a log-depth product tree (Reduction by matrix multiplication section).
  * The usage model is the state machine of the PARAMENT library section
  * (Fig. state_machine): create a context, set the Hamiltonians once, then
  * propagate any number of control sequences.

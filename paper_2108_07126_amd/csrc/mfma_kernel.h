@@ -14,13 +14,17 @@
 //      matrices), then squares s times,
 //   4. optionally stores U_j, and multiplies it into the team's chain
 //      product Q <- U_j Q (later slices on the left, eq. slices).
-// Operands of each complex product are staged in LDS (row stride D+1, split
-// re/im planes, conflict-free fragment reads) and multiplied as four real
-// products on MFMA (FP64: v_mfma_f64_16x16x4f64; FP32: v_mfma_f32_16x16x4f32).
-// Finally the chain products are reduced by a pairwise tree in FP64 whose
-// nodes meet through per-pair tickets: the second team to finish a pair
-// multiplies it (odd leftovers are carried up unchanged) -- the reduction of
-// the Reduction by matrix multiplication section, in one launch.
+// One-wave teams (D = 16) multiply straight from registers: register r of
+// a lane is the B operand of k-slice r, and the A operand of a Hermitian
+// left factor (or of U = C - i P) is formed from the lane's own registers.
+// Larger teams stage both operands in LDS (row stride D+1, split re/im
+// planes, conflict-free fragment reads).  Complex products run as three real
+// MFMA products (3M) in FP64, FP32-3M and BF16 split, four in plain FP32
+// (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32, v_mfma_f32_16x16x16_bf16).
+// Finally the blocks' chain products enter the ticketed FP64 product tree of
+// mfma_tree.h (fan-in 8: the last of eight consecutive nodes to arrive
+// multiplies them, a group of one moves up unchanged) -- the reduction of the
+// Reduction by matrix multiplication section, in the same launch.
 #include "mfma_tree.h"
 
 namespace pm {
