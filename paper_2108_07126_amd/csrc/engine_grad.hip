@@ -203,6 +203,68 @@ __device__ void pair_taylor(const Tile<double>& Gt, const Tile<double>& Et, int 
     dU = c_minus_is(dC, dS);
 }
 
+// pair_taylor for one-wave teams: the products whose left factor is
+// Hermitian (G, and the powers of Y = G^2) are taken straight from registers
+// (reg_mul_herm); the three with a general left factor (E G, dP Y, E S') are
+// staged as before.  Same series, same products.
+template <class G>
+__device__ void pair_taylor_reg(const Tile<double>& Gt, const Tile<double>& Et, int m, const Lane& L,
+                                double* s0, double* s1, Tile<double>& U, Tile<double>& dU) {
+    Tile<double> C = ident<double>(L), dC = tzero(), S, dS;
+    if (m <= 1) {
+        S = Gt;
+        dS = Et;
+    } else {
+        const int qc = m / 2, qs = (m - 1) / 2;
+        const Tile<double> Y = reg_mul_herm<double>(Gt, Gt);
+        const Tile<double> dY = tadd(reg_mul_herm<double>(Gt, Et), mul2<G>(Et, Gt, L, s0, s1));
+        Tile<double> Sp = ident<double>(L), dSp = tzero();
+        axpy(C, cos_coef(1), Y);
+        axpy(dC, cos_coef(1), dY);
+        if (qs >= 1) {
+            axpy(Sp, sin_coef(1), Y);
+            axpy(dSp, sin_coef(1), dY);
+        }
+        Tile<double> P = Y, dP = dY;
+        for (int k = 2; k <= qc; ++k) {
+            const Tile<double> Pn = reg_mul_herm<double>(P, Y);
+            const Tile<double> t1 = reg_mul_herm<double>(P, dY);   // P dY
+            const Tile<double> t2 = mul2<G>(dP, Y, L, s0, s1);     // dP Y
+            P = Pn;
+            dP = tadd(t1, t2);
+            axpy(C, cos_coef(k), P);
+            axpy(dC, cos_coef(k), dP);
+            if (k <= qs) {
+                axpy(Sp, sin_coef(k), P);
+                axpy(dSp, sin_coef(k), dP);
+            }
+        }
+        if (qs >= 1) {
+            S = reg_mul_herm<double>(Gt, Sp);
+            dS = tadd(reg_mul_herm<double>(Gt, dSp), mul2<G>(Et, Sp, L, s0, s1));   // G dS' + E S'
+        } else {
+            S = Gt;
+            dS = Et;
+        }
+    }
+    U = c_minus_is(C, S);
+    dU = c_minus_is(dC, dS);
+}
+
+// U_j = exp(-i G) from the scaled exponent Gt by the series and s squarings
+// (one-wave teams: the series in registers).
+template <class G>
+__device__ __forceinline__ Tile<double> slice_exp(const Tile<double>& Gt, int m, int s, const Lane& L, double* s0,
+                                                  double* s1) {
+    if constexpr (G::TW == 1) {
+        Tile<double> C, P;
+        taylor_parts_reg<double>(Gt, m, L, C, P);
+        return square_n<G, double>(combine_cp<double>(C, P), s, L, s0);
+    } else {
+        return square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
+    }
+}
+
 // Sum over the team of a per-lane value; uniform result.  red: LDS, TW doubles.
 template <class G>
 __device__ __forceinline__ double team_sum(double x, const Lane& L, double* red) {
@@ -337,7 +399,7 @@ backward_mfma(GradParams gp) {
         Tile<double> Gt;
         int m, s;
         slice_exponent(gather_samples(p, wr, j), Gt, m, s);
-        const Tile<double> U = square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
+        const Tile<double> U = slice_exp<G>(Gt, m, s, L, s0, s1);
         P = mul2<G>(U, P, L, s0, s1);
     }
     // Omega_{j0} = P Z P^H, Z = W^H U(T)
@@ -354,11 +416,12 @@ backward_mfma(GradParams gp) {
         int m, s;
         slice_exponent(cur, Gt, m, s);
         // U_j and Lambda_j = Omega_j U_j^H
-        Tile<double> U = square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
+        Tile<double> U = slice_exp<G>(Gt, m, s, L, s0, s1);
         const Tile<double> Lam = mul_adjB<G>(Om, U, L, s0, s1);
         // F_j = L_f(G_j, Lambda_j)
         Tile<double> Up, F;
-        pair_taylor<G>(Gt, tscale(Lam, -s), m, L, s0, s1, Up, F);
+        if constexpr (G::TW == 1) pair_taylor_reg<G>(Gt, tscale(Lam, -s), m, L, s0, s1, Up, F);
+        else pair_taylor<G>(Gt, tscale(Lam, -s), m, L, s0, s1, Up, F);
         for (int q = 0; q < s; ++q) {
             team_sync<G>();
             slot_store<G, double>(s0, Up, L);
