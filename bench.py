@@ -49,7 +49,7 @@ PEAK = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "fp32_3m": PEAK_FP32
 # valid only while the kernel's sources hash to the value they had then.
 TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_kernel.h", "mfma_tiles.h", "mfma_tree.h", "engine_common.h", "pm_internal.h"]
 MEASURED_TRAFFIC = {"bytes": (2.0 * 4452.515625 + 1.0 * 2360.53125) * 1024.0,
-                    "sources_sha256": "381436aa8cd6c099da85e17de4c80bc5357ff1dc7992484f99e726eab8f9f0ab",
+                    "sources_sha256": "71bb5a8361a990b82464b929e153d00db0a239e83f47f59f6225b56f6b6e040b",
                     "profile": "profiles/propagate_d16_random_qudit_traffic.md"}
 LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "cf4", "trajectory", "grad", "grape", "batch", "cpu",
         "fixed_error"]

@@ -603,15 +603,22 @@ __device__ Tile<double> cheb_exp(const Tile<double>& Gt, int m, double theta, co
         X.im[r] = Gt.im[r] * inv;
         D1.re[r] = D1.im[r] = D2.re[r] = D2.im[r] = keep.re[r] = keep.im[r] = 0.0;
     }
-    team_sync<G>();
-    slot_store<G, double>(s0, X, L);   // X stays in s0
+    if constexpr (G::TW != 1) {
+        team_sync<G>();
+        slot_store<G, double>(s0, X, L);   // X stays in s0
+    }
     for (int k = m; k >= 0; --k) {
         Tile<double> P;
         if (k < m) {
-            team_sync<G>();
-            slot_store<G, double>(s1, D1, L);
-            team_sync<G>();
-            P = slot_mul<G, double>(s0, s1, L);
+            if constexpr (G::TW == 1) {
+                // one-wave team: X is Hermitian, so X D1 comes from registers
+                P = reg_mul_herm<double>(X, D1);
+            } else {
+                team_sync<G>();
+                slot_store<G, double>(s1, D1, L);
+                team_sync<G>();
+                P = slot_mul<G, double>(s0, s1, L);
+            }
         } else {
 #pragma unroll
             for (int r = 0; r < 4; ++r) P.re[r] = P.im[r] = 0.0;
