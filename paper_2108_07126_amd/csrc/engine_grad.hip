@@ -415,9 +415,21 @@ backward_mfma(GradParams gp) {
         Tile<double> Gt;
         int m, s;
         slice_exponent(cur, Gt, m, s);
-        // U_j and Lambda_j = Omega_j U_j^H
-        Tile<double> U = slice_exp<G>(Gt, m, s, L, s0, s1);
-        const Tile<double> Lam = mul_adjB<G>(Om, U, L, s0, s1);
+        // U_j, Lambda_j = Omega_j U_j^H and Omega_{j+1} = U_j Omega_j U_j^H =
+        // U_j Lambda_j (one-wave teams without squarings: U_j Lambda_j from the
+        // series' Hermitian pair C - i P in registers)
+        Tile<double> Lam;
+        if constexpr (G::TW == 1) {
+            Tile<double> Cr, Pr;
+            taylor_parts_reg<double>(Gt, m, L, Cr, Pr);
+            const Tile<double> U = square_n<G, double>(combine_cp<double>(Cr, Pr), s, L, s0);
+            Lam = mul_adjB<G>(Om, U, L, s0, s1);
+            Om = s == 0 ? reg_mul_cp<double>(Cr, Pr, Lam) : mul2<G>(U, Lam, L, s0, s1);
+        } else {
+            const Tile<double> U = slice_exp<G>(Gt, m, s, L, s0, s1);
+            Lam = mul_adjB<G>(Om, U, L, s0, s1);
+            Om = mul2<G>(U, Lam, L, s0, s1);
+        }
         // F_j = L_f(G_j, Lambda_j)
         Tile<double> Up, F;
         if constexpr (G::TW == 1) pair_taylor_reg<G>(Gt, tscale(Lam, -s), m, L, s0, s1, Up, F);
@@ -440,8 +452,6 @@ backward_mfma(GradParams gp) {
             const double g = team_sum<G>(part, L, red);
             if (L.lane == 0 && L.wt == 0) gp.gw[j * p.M + mm] = g;
         }
-        // Omega_{j+1} = U_j Omega_j U_j^H
-        Om = mul_adjB<G>(mul2<G>(U, Om, L, s0, s1), U, L, s0, s1);
     }
 }
 
