@@ -173,6 +173,23 @@ def test_largest_basis_order4(pm, d):
     assert e <= 2 * tol32(n, d), (d, e)
 
 
+@pytest.mark.parametrize("d", [1, 2])
+def test_small_dims_per_slice_default_chains(pm, d):
+    """Per-slice output on dimensions 1 and 2 at the default decomposition
+    (one chain per resident wave, not the U(T)-only tuned count): about a
+    million slices with a ragged last chain, every slice and U(T) against
+    the oracle in FP64 and FP32."""
+    w = synth.random_system(d, 1, n_slices=(1 << 20) + 777, h=0.01, order=2, tag=90 + d)
+    Uo, slo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 2, return_slices=True)
+    U, sl = run(pm, w, slices=True)
+    assert orc.relative_frobenius(U, Uo) <= TOL64
+    assert np.max(np.abs(sl - slo)) <= 1e-13
+    U32v, sl32 = run(pm, w, precision=pm.PM_FP32, slices=True)
+    assert sl32.dtype == np.complex64
+    assert orc.relative_frobenius(U32v, Uo) <= tol32(w.n_slices, d)
+    assert np.max(np.abs(sl32 - slo)) <= 64 * U32
+
+
 @pytest.mark.parametrize("d", [1, 2, 3, 4])
 def test_small_dims_deep_tree(pm, d):
     """The small-dimension engine with about 150 leaves (three levels of the
