@@ -32,6 +32,18 @@ U = exp(-i H t), Computational approach section):
     whose combined exponent is M1 + i [M1, M2] up to O(h^5), the commutator
     Magnus exponent above; no commutator of the controls is formed.
     Scheme code CF4 (= 5) in the ``order`` argument.
+  - sixth-order Magnus (the higher-order Magnus integrators the Magnus
+    integrators section points to, with their extra commutators; the
+    three-node scheme of Blanes, Casas and Ros, BIT 2000): with the slice's
+    Hamiltonian sampled at the Gauss-Legendre nodes t_j + c_i h,
+    c = 1/2 - sqrt(15)/10, 1/2, 1/2 + sqrt(15)/10 (three samples per slice,
+    3N in all), and A_i = -i H(t_j + c_i h) the generator of Y' = A Y,
+        a1 = h A_2,  a2 = (sqrt(15) h / 3)(A_3 - A_1),
+        a3 = (10 h / 3)(A_3 - 2 A_2 + A_1),
+        C1 = [a1, a2],  C2 = -(1/60) [a1, 2 a3 + C1],
+        Omega = a1 + a3 / 12 + (1/240) [-20 a1 - a3 + C1, a2 + C2],
+    and G_j = i Omega (Hermitian), U_j = exp(Omega) = exp(-i G_j).
+    Scheme code M6 (= 6) in the ``order`` argument.
 * slice propagators U_j = exp(-i G_j) by Hermitian eigendecomposition:
   G = Q diag(lam) Q^H  =>  exp(-i G) = Q diag(exp(-i lam)) Q^H (the
   decomposition route of the Matrix exponential section: for Hermitian
@@ -56,6 +68,9 @@ __all__ = [
     "n_slices",
     "magnus4_exponent",
     "cf4_exponents",
+    "M6",
+    "GL3_NODES",
+    "magnus6_exponent",
     "slice_propagators",
     "slice_exponents",
     "expm_minus_i",
@@ -73,12 +88,22 @@ __all__ = [
 _CHUNK = 8192
 
 CF4 = 5   # scheme code of the commutator-free fourth-order integrator
+M6 = 6    # scheme code of the sixth-order Magnus integrator
+
+# Gauss-Legendre nodes of three points on [0, 1]: the sixth-order scheme's
+# sample positions within a slice
+GL3_NODES = (0.5 - 15.0 ** 0.5 / 10.0, 0.5, 0.5 + 15.0 ** 0.5 / 10.0)
 
 
 def n_slices(order: int, n_samples: int) -> int:
     """Slices covered by n_samples samples: one sample per slice for the
-    midpoint rule, three per slice (shared ends, 2N + 1 in all) otherwise."""
-    return n_samples if order == 2 else (n_samples - 1) // 2
+    midpoint rule, three per slice for the sixth-order scheme (3N in all),
+    three per slice with shared ends (2N + 1 in all) otherwise."""
+    if order == 2:
+        return n_samples
+    if order == M6:
+        return n_samples // 3
+    return (n_samples - 1) // 2
 
 
 def hamiltonian_samples(H0: np.ndarray, Hk: np.ndarray, samples: np.ndarray) -> np.ndarray:
@@ -102,6 +127,28 @@ def magnus4_exponent(A1: np.ndarray, A2: np.ndarray, A3: np.ndarray, h: float) -
     return (h / 6.0) * (A1 + 4.0 * A2 + A3) + 1j * (h * h / 12.0) * comm
 
 
+def magnus6_exponent(A1: np.ndarray, A2: np.ndarray, A3: np.ndarray, h: float) -> np.ndarray:
+    """Sixth-order Magnus exponent G (Hermitian, U = exp(-i G)) of a slice of
+    width h from H at its three Gauss-Legendre nodes (A1, A2, A3 = H at
+    t + c_1 h, t + c_2 h, t + c_3 h; batched over leading axes).
+
+    The steps are those of the scheme, in the notation of the Magnus
+    expansion for Y' = A Y with A = -i H: the three moments a1, a2, a3, the
+    commutators C1, C2, then Omega, and G = i Omega.
+    """
+    def comm(x, y):
+        return x @ y - y @ x
+    B1, B2, B3 = -1j * A1, -1j * A2, -1j * A3
+    r15 = 15.0 ** 0.5
+    a1 = h * B2
+    a2 = (r15 * h / 3.0) * (B3 - B1)
+    a3 = (10.0 * h / 3.0) * (B3 - 2.0 * B2 + B1)
+    C1 = comm(a1, a2)
+    C2 = -(1.0 / 60.0) * comm(a1, 2.0 * a3 + C1)
+    omega = a1 + a3 / 12.0 + (1.0 / 240.0) * comm(-20.0 * a1 - a3 + C1, a2 + C2)
+    return 1j * omega
+
+
 def slice_exponents(H0, Hk, samples, h: float, order: int, start: int = 0, stop: int | None = None) -> np.ndarray:
     """Hermitian slice exponents G_j for slices [start, stop)."""
     samples = np.asarray(samples, dtype=np.float64)
@@ -114,7 +161,12 @@ def slice_exponents(H0, Hk, samples, h: float, order: int, start: int = 0, stop:
         stop = n if stop is None else stop
         A = hamiltonian_samples(H0, Hk, samples[:, 2 * start: 2 * stop + 1])
         return magnus4_exponent(A[0:-1:2], A[1::2], A[2::2], h)
-    raise ValueError("order must be 2 or 4")
+    if order == M6:
+        n = samples.shape[1] // 3
+        stop = n if stop is None else stop
+        A = hamiltonian_samples(H0, Hk, samples[:, 3 * start: 3 * stop])
+        return magnus6_exponent(A[0::3], A[1::3], A[2::3], h)
+    raise ValueError("order must be 2, 4 or 6")
 
 
 def cf4_exponents(H0, Hk, samples, h: float, start: int = 0, stop: int | None = None):
@@ -243,6 +295,8 @@ def control_gradient(H0, Hk, samples, h: float, order: int, W: np.ndarray):
     samples = np.asarray(samples, np.float64)
     if order == CF4:
         return _control_gradient_cf4(H0, Hk, samples, h, W)
+    if order == M6:
+        raise NotImplementedError("the sixth-order scheme has no gradient here")
     n = n_slices(order, samples.shape[1])
     d = H0.shape[0]
     G = slice_exponents(H0, Hk, samples, h, order)

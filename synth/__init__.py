@@ -13,7 +13,10 @@ library expects them: ``samples[k, i]`` is control k at sample i, with
 
 * order 2 (midpoint rule): n_samples = N, sample j at t = (j + 1/2) h;
 * order 4 (Simpson + commutator Magnus): n_samples = 2N + 1, sample i at
-  t = i h / 2, slice j using samples 2j, 2j+1, 2j+2.
+  t = i h / 2, slice j using samples 2j, 2j+1, 2j+2;
+* order 6 (sixth-order Magnus): n_samples = 3N, samples 3j, 3j+1, 3j+2 at
+  the Gauss-Legendre nodes t = (j + c_i) h of slice j,
+  c = 1/2 - sqrt(15)/10, 1/2, 1/2 + sqrt(15)/10.
 
 Random draws use ``numpy.random.default_rng([SEED_BASE, tag])`` in a fixed
 order: H0, then H_1..H_K, then control parameters, then the target.
@@ -58,7 +61,11 @@ class Workload:
 
     @property
     def n_slices(self) -> int:
-        return self.n_samples if self.order == 2 else (self.n_samples - 1) // 2
+        if self.order == 2:
+            return self.n_samples
+        if self.order == 6:
+            return self.n_samples // 3
+        return (self.n_samples - 1) // 2
 
 
 def rng_for(tag) -> np.random.Generator:
@@ -81,10 +88,17 @@ def haar_unitary(rng: np.random.Generator, d: int) -> np.ndarray:
     return q * ph[None, :]
 
 
+GL3 = (0.5 - math.sqrt(15.0) / 10.0, 0.5, 0.5 + math.sqrt(15.0) / 10.0)
+
+
 def sample_times(n_slices: int, h: float, order: int) -> np.ndarray:
-    """Times at which the controls are sampled (midpoints, or half-slice grid)."""
+    """Times at which the controls are sampled (midpoints, the half-slice
+    grid, or three Gauss-Legendre nodes per slice for order 6)."""
     if order == 2:
         return (np.arange(n_slices, dtype=np.float64) + 0.5) * h
+    if order == 6:
+        j = np.arange(n_slices, dtype=np.float64)[:, None]
+        return ((j + np.array(GL3)[None, :]) * h).reshape(-1)
     return np.arange(2 * n_slices + 1, dtype=np.float64) * (0.5 * h)
 
 
