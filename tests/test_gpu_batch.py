@@ -7,6 +7,7 @@ import pytest
 
 import oracle.propagator as orc
 import synth
+from bounds import max_squarings, tol
 
 pytestmark = pytest.mark.gpu
 
@@ -34,23 +35,6 @@ def mixed_instances():
     return out
 
 
-def tol(prec, n, d, s=0):
-    """Error bound of a reduced-precision path (see test_gpu_precision); s
-    squarings multiply the Taylor step's relative error by 2^s."""
-    if prec == 0:
-        return 1e-10
-    if prec == 3:
-        return (16 * math.sqrt(n) * math.sqrt(d) * 2.0 ** -16 + 1e-4) * 2 ** s
-    c3m = 2.0 if prec == 2 else 1.0   # 3M: imaginary parts on the (|Ar|+|Ai|)(|Br|+|Bi|) scale
-    return (4 * math.sqrt(n) * d * 2.0 ** -24 * c3m + 1e-6) * 2 ** s
-
-
-def max_squarings(pm, w, prec):
-    G = orc.slice_exponents(w.H0, w.Hk, w.samples, w.h, w.order)
-    nu = float(np.max(np.sum(np.abs(G), axis=1)))
-    return pm.plan_expm(nu, prec, n_slices=w.n_slices)[1]
-
-
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])
 def test_batch_matches_oracle(pm, prec):
     ws = mixed_instances()
@@ -63,8 +47,10 @@ def test_batch_matches_oracle(pm, prec):
     for w, U in zip(ws, Us):
         Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, w.order)
         e = orc.relative_frobenius(U, Uo)
-        worst = max(worst, e / tol(prec, w.n_slices, w.dim))
-        assert e <= tol(prec, w.n_slices, w.dim), (w.name, w.n_slices, e)
+        # packets share one plan per step: at most the instance's largest s
+        s = 0 if prec == 0 else max_squarings(pm, w, prec)
+        worst = max(worst, e / tol(prec, w.n_slices, w.dim, s))
+        assert e <= tol(prec, w.n_slices, w.dim, s), (w.name, w.n_slices, e)
     say(f"  worst error / bound {worst:.3f}")
 
 

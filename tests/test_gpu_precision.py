@@ -1,19 +1,5 @@
-"""Reduced-precision paths against the FP64 oracle.
-
-These paths have no oracle of their own; each result's error against the
-FP64 oracle must stay inside a bound derived from its arithmetic:
-
-* FP32 products: every entry of a complex product of unit-norm rows and
-  columns is a d-term sum rounded at u32 = 2^-24, about four products per
-  slice, and the N slice propagators' errors add up like a random walk:
-      tol(N, d) = 4 sqrt(N) d u32 + 1e-6;
-  3M products carry their imaginary parts on the (|Ar|+|Ai|)(|Br|+|Bi|)
-  scale, twice that bound.
-* BF16 split (hi*hi + hi*lo + lo*hi, FP32 accumulation): the dropped lo*lo
-  term and the split residues leave ~2^-16 relative error per real product,
-  and about four products per slice:
-      tol(N, d) = 16 sqrt(N) sqrt(d) 2^-16 + 1e-4.
-The measured errors are printed for the record.
+"""Reduced-precision paths against the FP64 oracle, within the bounds of
+tests/bounds.py (derived from the arithmetic; measured errors are printed).
 """
 import math
 import sys
@@ -23,15 +9,9 @@ import pytest
 
 import oracle.propagator as orc
 import synth
+from bounds import max_squarings, tol, tol_slice
 
 pytestmark = pytest.mark.gpu
-
-
-def tol(prec, n, d, pm):
-    if prec == pm.PM_BF16_SPLIT:
-        return 16 * math.sqrt(n) * math.sqrt(d) * 2.0 ** -16 + 1e-4
-    c3m = 2.0 if prec == pm.PM_FP32_3M else 1.0
-    return 4 * math.sqrt(n) * d * 2.0 ** -24 * c3m + 1e-6
 
 
 @pytest.fixture(scope="module")
@@ -58,11 +38,13 @@ def test_reduced_precision_error_bounds(pm, d, order):
         e = orc.relative_frobenius(U, Uo)
         es = float(np.max(np.abs(sl - slo)))
         errs[prec] = e
-        print(f"  prec={prec} U(T) rel err {e:.3e} (bound {tol(prec, n, d, pm):.3e}), slice max err {es:.2e}",
-              file=sys.stderr, flush=True)
-        assert e <= tol(prec, n, d, pm)
-        assert es <= tol(prec, 1, d, pm) * 4
-        assert orc.unitarity_defect(U) <= 10 * tol(prec, n, d, pm)
+        sq = max_squarings(pm, w, prec)
+        print(f"  prec={prec} s={sq} U(T) rel err {e:.3e} (bound {tol(prec, n, d, sq):.3e}), "
+              f"slice max err {es:.2e} (bound {tol_slice(prec, d, sq):.2e})", file=sys.stderr, flush=True)
+        assert e <= tol(prec, n, d, sq)
+        assert es <= tol_slice(prec, d, sq)
+        # ||U^H U - I||_F <= 2 ||U - Uo||_F + O(err^2) = 2 sqrt(d) rel err
+        assert orc.unitarity_defect(U) <= 2.5 * math.sqrt(d) * tol(prec, n, d, sq)
     # BF16 split carries fewer significant bits than FP32
     assert errs[pm.PM_BF16_SPLIT] >= 0.5 * errs[pm.PM_FP32]
 
@@ -76,4 +58,4 @@ def test_precision_sweep_workload_all_modes(pm):
             ctx.set_hamiltonian(w.H0, w.Hk, 2)
             e = orc.relative_frobenius(ctx.equiprop(w.samples, w.h), Uo)
         print(f"  precision sweep prec={prec}: rel err {e:.3e}", file=sys.stderr, flush=True)
-        assert e <= (1e-10 if prec == pm.PM_FP64 else tol(prec, 256, 64, pm))
+        assert e <= tol(prec, 256, 64, max_squarings(pm, w, prec))
