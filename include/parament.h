@@ -10,7 +10,9 @@
  *      (order 2) or by 4th-order commutator Magnus with Simpson quadrature
  *      (order 4, Magnus integrators section, eq. magnus_coeffs), or -- the
  *      commutator-free alternative the same section names -- two
- *      exponents per slice without commutators (PM_ORDER_CF4);
+ *      exponents per slice without commutators (PM_ORDER_CF4), or by the
+ *      sixth-order Magnus scheme the same section points to for higher
+ *      order (PM_ORDER_MAGNUS6);
  *   2. exponentiate all slices at once, U_j = exp(-i G_j), by scaling and
  *      squaring with a truncated Taylor series (Matrix exponential section);
  *   3. reduce U(T) = U_{N-1} ... U_1 U_0 (eq. slices) by chunked products and
@@ -27,7 +29,9 @@
  *     contiguous).  Order 2: n_samples = N, sample j is H's control value at
  *     the slice midpoint (j + 1/2) h.  Order 4: n_samples = 2N + 1 (odd,
  *     >= 3), sample i at t = i h / 2; slice j uses samples 2j, 2j+1, 2j+2.
- *     PM_ORDER_CF4 samples exactly as order 4.
+ *     PM_ORDER_CF4 samples exactly as order 4.  PM_ORDER_MAGNUS6:
+ *     n_samples = 3N, samples 3j, 3j+1, 3j+2 at the Gauss-Legendre nodes
+ *     t = (j + c_i) h, c = 1/2 - sqrt(15)/10, 1/2, 1/2 + sqrt(15)/10.
  *   - dt is the slice width h for every order (for order 4 the paper's
  *     sample spacing is h/2).
  *   - Product order: later slices multiply from the left.
@@ -62,7 +66,21 @@ enum {
      * whose exponents are built from H0, H_k alone (basis 1 + n_ctrl).  The
      * 2N exponentials are propagated as the factors of the product in
      * order; per-slice output is not available (PM_E_INVALID_ARG).        */
-    PM_ORDER_CF4 = 5
+    PM_ORDER_CF4 = 5,
+    /* Sixth-order Magnus (the higher-order Magnus integrators the Magnus
+     * integrators section points to; the three-node scheme of Blanes, Casas
+     * and Ros).  With A1, A2, A3 = H at the slice's Gauss-Legendre nodes,
+     * the moments P1 = h A2, P2 = (sqrt(15) h/3)(A3 - A1) and
+     * P3 = (10 h/3)(A3 - 2 A2 + A1) give R1 = -i[P1, P2],
+     * R2 = (i/60)[P1, 2 P3 + R1] and the slice exponent
+     *   G_j = P1 + P3/12 - (i/240)[-20 P1 - P3 + R1, P2 + R2],
+     * formed on the device from the basis {H0, H_k} (1 + n_ctrl matrices)
+     * by three products per slice, then exponentiated like every other
+     * exponent.  PM_FP64 contexts only (pm_set_hamiltonian returns
+     * PM_E_UNSUPPORTED otherwise); per-slice output is available; the
+     * gradient, trajectory, GRAPE and batch entry points do not take it
+     * (PM_E_UNSUPPORTED).                                                 */
+    PM_ORDER_MAGNUS6 = 6
 };
 
 typedef enum pm_status {
@@ -112,7 +130,8 @@ pm_status pm_destroy(pm_ctx *ctx);
 
 /* Upload the drift H0 [dim][dim] and controls Hk [n_ctrl][dim][dim]
  * (complex128, Hermitian; Hk may be NULL when n_ctrl == 0) and choose the
- * integrator (PM_ORDER_MIDPOINT, PM_ORDER_MAGNUS4 or PM_ORDER_CF4).  For order 4 the
+ * integrator (PM_ORDER_MIDPOINT, PM_ORDER_MAGNUS4, PM_ORDER_CF4 or
+ * PM_ORDER_MAGNUS6).  For order 4 the
  * host forms the effective control Hamiltonians of eq. magnus_coeffs,
  * i[H0,H_k] and i[H_k,H_k'] (k<k'), all Hermitian, and uploads them too
  * (setHamiltonian of the PARAMENT library section).  Inputs are symmetrised
@@ -311,7 +330,7 @@ const char *pm_last_error(const pm_ctx *ctx);
 
 /* ---- host-only helpers: no GPU is touched ------------------------------ */
 
-/* Number of Hermitian basis matrices: 1 + n_ctrl (order 2 and CF4), or
+/* Number of Hermitian basis matrices: 1 + n_ctrl (order 2, CF4 and 6), or
  * 1 + 2 n_ctrl + n_ctrl (n_ctrl - 1) / 2 (order 4, eq. magnus_coeffs:
  * 3K/2 + K^2/2 effective controls besides H0).  -1 on bad arguments. */
 int64_t pm_basis_count(int64_t n_ctrl, int order);
@@ -335,7 +354,11 @@ pm_status pm_build_basis_host(int64_t dim, const double *H0, int64_t n_ctrl,
  *   w_H0 = h, w_Hk = (h/6)(s0_k + 4 s1_k + s2_k),
  *   w_i[H0,Hk] = (h^2/12)(s2_k - s0_k),
  *   w_i[Hk,Hk'] = (h^2/12)(s0_k s2_k' - s2_k s0_k').
- * weights_out [M]. */
+ * weights_out [M]; for PM_ORDER_MAGNUS6 weights_out [3][M] receives the
+ * weights of the moments P1, P2, P3 (see PM_ORDER_MAGNUS6) with
+ * s1, s2, s3 = samples 3j, 3j+1, 3j+2:
+ *   P1: (h, h s2_k),  P2: (0, (sqrt(15) h/3)(s3_k - s1_k)),
+ *   P3: (0, (10 h/3)(s3_k - 2 s2_k + s1_k)). */
 pm_status pm_slice_weights_host(int64_t n_ctrl, const double *samples,
                                 int64_t n_samples, double dt, int order,
                                 int64_t slice, double *weights_out);

@@ -24,7 +24,7 @@ PM_FP64, PM_FP32, PM_FP32_3M, PM_BF16_SPLIT = 0, 1, 2, 3
 PM_EXPM_TAYLOR, PM_EXPM_CHEBYSHEV = 0, 1
 PM_TRAJ_PROPAGATORS, PM_TRAJ_STATES, PM_TRAJ_DENSITY = 0, 1, 2
 PM_OPT_GD, PM_OPT_ADAM = 0, 1
-PM_ORDER_MIDPOINT, PM_ORDER_MAGNUS4, PM_ORDER_CF4 = 2, 4, 5
+PM_ORDER_MIDPOINT, PM_ORDER_MAGNUS4, PM_ORDER_CF4, PM_ORDER_MAGNUS6 = 2, 4, 5, 6
 MAX_CHEBYSHEV_DEGREE = 25
 PRECISIONS = {"fp64": PM_FP64, "fp32": PM_FP32, "fp32_3m": PM_FP32_3M, "bf16_split": PM_BF16_SPLIT}
 STATUS = ["PM_OK", "PM_E_INVALID_ARG", "PM_E_NOT_READY", "PM_E_NOT_HERMITIAN", "PM_E_OOM",
@@ -174,9 +174,12 @@ def build_basis_host(H0, Hk, order: int) -> Tuple[np.ndarray, np.ndarray]:
 
 
 def slice_weights_host(samples, dt: float, order: int, slice_index: int) -> np.ndarray:
+    """Weights of one exponent on the basis ([M]; order 6: [3][M], the
+    moments P1, P2, P3)."""
     s = np.ascontiguousarray(np.asarray(samples, np.float64))
     K, S = s.shape
-    w = np.zeros(basis_count(K, order))
+    M = basis_count(K, order)
+    w = np.zeros((3, M) if order == PM_ORDER_MAGNUS6 else M)
     _check(_lib.pm_slice_weights_host(K, _ptr(s) if K else None, S, dt, order, slice_index, _ptr(w)))
     return w
 
@@ -209,8 +212,13 @@ def plan_chebyshev(nu: float, precision: int = PM_FP64, max_degree: int = MAX_CH
 
 
 def n_slices(n_samples: int, order: int) -> int:
-    """Slices covered by n_samples samples (2N + 1 samples for order 4 and CF4)."""
-    return n_samples if order == 2 else (n_samples - 1) // 2
+    """Slices covered by n_samples samples (2N + 1 samples for order 4 and
+    CF4, 3N for order 6)."""
+    if order == 2:
+        return n_samples
+    if order == PM_ORDER_MAGNUS6:
+        return n_samples // 3
+    return (n_samples - 1) // 2
 
 
 # ------------------------------------------------------------------ context

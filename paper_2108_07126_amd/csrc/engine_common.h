@@ -200,8 +200,9 @@ __device__ __forceinline__ void plan_cheb_lanes(const PropParams& p, double nu, 
 // formula of its basis matrix.  Lanes m >= M get weight 0.
 struct WeightRecipe {
     int kind;        // 0: H0, 1: order-2 control, 2: Simpson, 3: commutator with H0, 4: pair, 5: none,
-                     // 6: commutator-free control
-    int64_t xa, xb;  // sample offsets of controls a, b (before adding the slice position)
+                     // 6: commutator-free control, 7: sixth-order moment of a control
+    int64_t xa, xb;  // sample offsets of controls a, b (before adding the slice position);
+                     // sixth order: xb is the moment (0, 1, 2)
 };
 
 struct SliceSamples {
@@ -281,6 +282,44 @@ __device__ __forceinline__ double combine_weight(const PropParams& p, const Weig
     w = r.kind == 3 ? w3 : w;
     w = r.kind == 4 ? w4 : w;
     return w;
+}
+
+// Sixth-order Magnus (PM_ORDER_MAGNUS6): slice j has the samples 3j, 3j+1,
+// 3j+2 of each control, taken at the Gauss-Legendre nodes of the slice, and
+// three moments of H over it are formed on the basis {H0, H_k}:
+//   P1 = h A2,  P2 = (sqrt(15) h / 3)(A3 - A1),  P3 = (10 h / 3)(A3 - 2 A2 + A1),
+// with A_i = H at node i (H0 enters P1 only).  Lane 16 q + m (q < 3, m < M)
+// gathers the samples of control m - 1 and combines the weight of basis
+// matrix m in moment q + 1; other lanes get weight 0.
+constexpr double kSqrt15 = 3.872983346207417;
+
+__device__ __forceinline__ WeightRecipe m6_recipe(const PropParams& p, int lane) {
+    WeightRecipe r;
+    const int q = lane >> 4, m = lane & 15;
+    r.xb = q;
+    r.xa = m >= 1 ? (int64_t)(m - 1) * p.n_samples : 0;
+    r.kind = (q > 2 || m >= p.M) ? 5 : (m == 0 ? 0 : 7);
+    return r;
+}
+
+__device__ __forceinline__ SliceSamples m6_gather(const PropParams& p, const WeightRecipe& r, int64_t j) {
+    SliceSamples v{0.0, 0.0, 0.0, 0.0, 0.0};
+    if (p.K == 0) return v;
+    const double* a = p.samples + r.xa + 3 * j;
+    v.x0 = a[0];
+    v.x1 = a[1];
+    v.x2 = a[2];
+    return v;
+}
+
+__device__ __forceinline__ double m6_weight(const PropParams& p, const WeightRecipe& r, const SliceSamples& v) {
+    const double h = p.h;
+    const double c1 = h * v.x1;
+    const double c2 = (h * (kSqrt15 / 3.0)) * (v.x2 - v.x0);
+    const double c3 = (h * (10.0 / 3.0)) * ((v.x2 - 2.0 * v.x1) + v.x0);
+    double w = r.xb == 0 ? c1 : (r.xb == 1 ? c2 : c3);
+    w = r.kind == 0 ? (r.xb == 0 ? h : 0.0) : w;
+    return r.kind == 5 ? 0.0 : w;
 }
 
 // DPP row rotation (within each row of 16 lanes) of a double.

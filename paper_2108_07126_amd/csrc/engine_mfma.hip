@@ -1,5 +1,5 @@
 // MFMA engine: the non-paired instances of the propagation kernel and the
-// dispatch over dimension, precision, method and pairing.
+// dispatch over dimension, precision, method, pairing and integrator.
 #include "mfma_kernel.h"
 
 namespace pm {
@@ -15,8 +15,13 @@ hipError_t launch_dims(int D, const PropParams& p, hipStream_t stream) {
 }
 
 hipError_t launch_mfma_pair(int precision, const PropParams& p, hipStream_t stream);
+hipError_t launch_mfma_m6(int D, const PropParams& p, hipStream_t stream);
 
 hipError_t launch_mfma(int D, int precision, const PropParams& p, hipStream_t stream) {
+    if (p.order == kOrderM6) {
+        if (precision != PM_FP64 || p.pair) return hipErrorInvalidValue;
+        return launch_mfma_m6(D, p, stream);
+    }
     if (p.pair) {
         if (D != 16) return hipErrorInvalidValue;
         return launch_mfma_pair(precision, p, stream);

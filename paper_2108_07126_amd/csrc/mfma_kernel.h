@@ -47,7 +47,13 @@ constexpr int min_waves_per_eu() {
 // slice's weights and lanes 32-63 the second's, and a lane expands with the
 // weights of the block its column lies in.  At the end the halves' products
 // are multiplied (second on the left) into the usual embedded chain product.
-template <typename T, int D, int NT, bool BL, int PMODE, bool CH, bool PAIR>
+//
+// M6 (FP64, PM_ORDER_MAGNUS6): the expand step forms the slice's three
+// Hermitian moments P1, P2, P3 on the basis {H0, H_k} (three weights per
+// basis matrix, gathered by lanes 16 q + m), and the exponent is the
+// sixth-order Magnus combination of magnus6_exponent (three commutators by
+// product and adjoint); the plan, the series and the chain are unchanged.
+template <typename T, int D, int NT, bool BL, int PMODE, bool CH, bool PAIR, bool M6>
 __global__ void __launch_bounds__(64 * (D / 16) * (D / 16) * NT)
 __attribute__((amdgpu_waves_per_eu(min_waves_per_eu<T, D>(), 8)))
 propagate_mfma(PropParams p) {
@@ -83,6 +89,7 @@ propagate_mfma(PropParams p) {
     const int64_t j0 = min(p.n_slices, chain * p.chunk);
     const int64_t j1 = min(p.n_slices, j0 + p.chunk);
     static_assert(!PAIR || D == 16, "slice pairs live in the 16-wide tile");
+    static_assert(!M6 || (std::is_same<T, double>::value && !PAIR), "sixth order: FP64, one slice per tile");
     // PAIR: halves [j0, jm) and [jm, j1); otherwise one run [j0, j1)
     const int64_t jm = PAIR ? j0 + (j1 - j0 + 1) / 2 : j1;
     const int64_t steps = jm - j0;
@@ -99,22 +106,57 @@ propagate_mfma(PropParams p) {
     Tile<double> Qx = ident_as<T>(L);
     // lane m < M gathers and combines the weight of basis matrix m; the next
     // slice's samples are loaded while this slice is exponentiated
-    const WeightRecipe wr = weight_recipe(p, PAIR ? (L.lane & 31) : L.lane);
+    WeightRecipe wr;
+    if constexpr (M6) wr = m6_recipe(p, L.lane);
+    else wr = weight_recipe(p, PAIR ? (L.lane & 31) : L.lane);
+    auto gather = [&](int64_t j) {
+        if constexpr (M6) return m6_gather(p, wr, j);
+        else return gather_samples(p, wr, j);
+    };
     const double lth = lane_theta_of(p, L.lane);
     const double lcth = lane_ctheta_of(p, L.lane);
-    SliceSamples smp = gather_samples(p, wr, min(wbase, jlast));
+    SliceSamples smp = gather(min(wbase, jlast));
     // output of the step's slice(s); the second block's slice in PAIR mode
     auto store_out = [&](int64_t t, const Tile<T>& U) {
         if constexpr (PAIR) store_slice_pair<G, T>(p, j0 + t, jm + t < j1 ? jm + t : -1, U, L);
         else store_slice<G, T>(p, j0 + t, U, L);
     };
     for (int64_t t = 0; t < steps; ++t) {
-        const double wl = wbase + t < wend ? combine_weight(p, wr, smp) : 0.0;
-        if (t + 1 < steps) smp = gather_samples(p, wr, min(wbase + t + 1, jlast));
+        double wl;
+        if constexpr (M6) wl = wbase + t < wend ? m6_weight(p, wr, smp) : 0.0;
+        else wl = wbase + t < wend ? combine_weight(p, wr, smp) : 0.0;
+        if (t + 1 < steps) smp = gather(min(wbase + t + 1, jlast));
         // expand (FP64)
         double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
         const int64_t bofs = mfma_basis_index(D, 0, L.TI, L.TJ, 0, 0, L.lane);
-        {
+        if constexpr (M6) {
+            // the three moments from one pass over the basis, then the
+            // sixth-order exponent
+            Tile<double> P1, P2, P3;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) P1.re[r] = P1.im[r] = P2.re[r] = P2.im[r] = P3.re[r] = P3.im[r] = 0.0;
+            const double* bb = bas + bofs;
+            constexpr int64_t STR = G::TW * 512;
+            for (int m = 0; m < p.M; ++m) {
+                const double w1 = readlane_d(wl, m), w2 = readlane_d(wl, 16 + m), w3 = readlane_d(wl, 32 + m);
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const double xr = bb[m * STR + r * 64], xi = bb[m * STR + 256 + r * 64];
+                    P1.re[r] = fma(w1, xr, P1.re[r]);
+                    P1.im[r] = fma(w1, xi, P1.im[r]);
+                    P2.re[r] = fma(w2, xr, P2.re[r]);
+                    P2.im[r] = fma(w2, xi, P2.im[r]);
+                    P3.re[r] = fma(w3, xr, P3.re[r]);
+                    P3.im[r] = fma(w3, xi, P3.im[r]);
+                }
+            }
+            const Tile<double> Gm = magnus6_exponent<G>(P1, P2, P3, L, s0, s1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                gre[r] = Gm.re[r];
+                gim[r] = Gm.im[r];
+            }
+        } else {
             // four basis matrices' entries are loaded before their FMAs, so
             // the load latencies overlap; the sum still runs in order of m
             const double* bb = bas + bofs;
@@ -258,28 +300,28 @@ constexpr size_t lds_fixed_bytes() {
     return sizeof(double) * ((size_t)NT * 2 * G::SLOT + (size_t)G::TD * D + 2);
 }
 
-template <typename T, int D, int NT, bool BL, int PMODE, bool CH, bool PAIR>
+template <typename T, int D, int NT, bool BL, int PMODE, bool CH, bool PAIR, bool M6>
 hipError_t launch_one(const PropParams& p, hipStream_t stream) {
     using G = Geo<D, NT>;
     const size_t lds = lds_fixed_bytes<D, NT>() + (BL ? sizeof(double) * (size_t)p.M * G::TW * 512 : 0);
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)propagate_mfma<T, D, NT, BL, PMODE, CH, PAIR>,
+        hipError_t e = hipFuncSetAttribute((const void*)propagate_mfma<T, D, NT, BL, PMODE, CH, PAIR, M6>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
-    hipLaunchKernelGGL((propagate_mfma<T, D, NT, BL, PMODE, CH, PAIR>), dim3((unsigned)p.n_leaves), dim3(G::THREADS), lds,
-                       stream, p);
+    hipLaunchKernelGGL((propagate_mfma<T, D, NT, BL, PMODE, CH, PAIR, M6>), dim3((unsigned)p.n_leaves),
+                       dim3(G::THREADS), lds, stream, p);
     return hipGetLastError();
 }
 
-template <typename T, int D, int NT, int PMODE, bool CH, bool PAIR = false>
+template <typename T, int D, int NT, int PMODE, bool CH, bool PAIR = false, bool M6 = false>
 hipError_t launch_bl(const PropParams& p, hipStream_t stream) {
     if constexpr (D == 16) {
-        if (p.basis_lds) return launch_one<T, D, NT, true, PMODE, CH, PAIR>(p, stream);
+        if (p.basis_lds) return launch_one<T, D, NT, true, PMODE, CH, PAIR, M6>(p, stream);
     }
-    return launch_one<T, D, NT, false, PMODE, CH, PAIR>(p, stream);
+    return launch_one<T, D, NT, false, PMODE, CH, PAIR, M6>(p, stream);
 }
 
 // The Chebyshev series is an FP64 method.

@@ -793,5 +793,83 @@ __device__ __forceinline__ Tile<double> node_load(const double* node, const Lane
     return t;
 }
 
+// Z - Z^H for a tile set Z (FP64): the adjoint is read back transposed from
+// an LDS slot.  For Hermitian X and Y, (XY)^H = YX, so the commutator
+// [X, Y] is XY - (XY)^H: one product instead of two.
+template <class G>
+__device__ __forceinline__ Tile<double> minus_adjoint(const Tile<double>& Z, const Lane& L, double* slot) {
+    team_sync<G>();
+    slot_store<G, double>(slot, Z, L);
+    team_sync<G>();
+    const double* re = slot;
+    const double* im = slot + G::PLANE;
+    const int col = 16 * L.TJ + L.j;
+    Tile<double> o;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        o.re[r] = Z.re[r] - re[col * G::LD + row];
+        o.im[r] = Z.im[r] + im[col * G::LD + row];
+    }
+    return o;
+}
+
+// X Y for a Hermitian X (FP64): from registers on one-wave teams, staged
+// through slots s0, s1 otherwise.
+template <class G>
+__device__ __forceinline__ Tile<double> herm_mul(const Tile<double>& X, const Tile<double>& Y, const Lane& L,
+                                                 double* s0, double* s1) {
+    if constexpr (G::TW == 1) {
+        return reg_mul_herm<double>(X, Y);
+    } else {
+        team_sync<G>();
+        slot_store<G, double>(s0, X, L);
+        slot_store<G, double>(s1, Y, L);
+        team_sync<G>();
+        return slot_mul<G, double>(s0, s1, L);
+    }
+}
+
+// The sixth-order Magnus exponent of a slice (three-node scheme of Blanes,
+// Casas and Ros) from its Hermitian moments P1, P2, P3 (the weights of
+// m6_weight).  With a_q = -i P_q, the scheme's
+//   C1 = [a1, a2],  C2 = -(1/60) [a1, 2 a3 + C1],
+//   Omega = a1 + a3 / 12 + (1/240) [-20 a1 - a3 + C1, a2 + C2]
+// reads, on Hermitian R1 = i C1 and R2 = i C2 and G = i Omega,
+//   R1 = -i [P1, P2],  R2 = (i/60) [P1, 2 P3 + R1],
+//   G = P1 + P3 / 12 - (i/240) [-20 P1 - P3 + R1, P2 + R2],
+// three commutators of Hermitian matrices, each one product and an adjoint.
+// Uses slots s0, s1.
+template <class G>
+__device__ Tile<double> magnus6_exponent(const Tile<double>& P1, const Tile<double>& P2, const Tile<double>& P3,
+                                         const Lane& L, double* s0, double* s1) {
+    Tile<double> K = minus_adjoint<G>(herm_mul<G>(P1, P2, L, s0, s1), L, s0);
+    Tile<double> R1, W;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        R1.re[r] = K.im[r];
+        R1.im[r] = -K.re[r];
+        W.re[r] = 2.0 * P3.re[r] + R1.re[r];
+        W.im[r] = 2.0 * P3.im[r] + R1.im[r];
+    }
+    K = minus_adjoint<G>(herm_mul<G>(P1, W, L, s0, s1), L, s0);
+    Tile<double> X, Y;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        X.re[r] = (-20.0 * P1.re[r] - P3.re[r]) + R1.re[r];
+        X.im[r] = (-20.0 * P1.im[r] - P3.im[r]) + R1.im[r];
+        Y.re[r] = P2.re[r] - K.im[r] * (1.0 / 60.0);
+        Y.im[r] = P2.im[r] + K.re[r] * (1.0 / 60.0);
+    }
+    K = minus_adjoint<G>(herm_mul<G>(X, Y, L, s0, s1), L, s0);
+    Tile<double> Gt;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        Gt.re[r] = (P1.re[r] + P3.re[r] * (1.0 / 12.0)) + K.im[r] * (1.0 / 240.0);
+        Gt.im[r] = (P1.im[r] + P3.im[r] * (1.0 / 12.0)) - K.re[r] * (1.0 / 240.0);
+    }
+    return Gt;
+}
+
 }  // namespace
 }  // namespace pm

@@ -362,13 +362,16 @@ pm_status ensure(pm_ctx* ctx, void** ptr, size_t* have, size_t need, const char*
 }
 
 bool order_ok(int order) {
-    return order == PM_ORDER_MIDPOINT || order == PM_ORDER_MAGNUS4 || order == PM_ORDER_CF4;
+    return order == PM_ORDER_MIDPOINT || order == PM_ORDER_MAGNUS4 || order == PM_ORDER_CF4 ||
+           order == PM_ORDER_MAGNUS6;
 }
 
 // Slices covered by n_samples samples (one per slice for the midpoint rule,
-// 2N + 1 otherwise).
+// three per slice for sixth order, 2N + 1 otherwise).
 int64_t n_slices_of(int order, int64_t n_samples) {
-    return order == 2 ? n_samples : (n_samples - 1) / 2;
+    if (order == 2) return n_samples;
+    if (order == PM_ORDER_MAGNUS6) return n_samples / 3;
+    return (n_samples - 1) / 2;
 }
 
 // Exponentials the kernels evaluate: one per slice, two for CF4 (the
@@ -378,15 +381,23 @@ int64_t n_exps_of(int order, int64_t n_samples) {
     return order == PM_ORDER_CF4 ? 2 * N : N;
 }
 
+// Sample counts the integrator accepts: N >= 1 (order 2), 2N + 1 (orders 4
+// and CF4), 3N (order 6).
+bool samples_ok(int order, int64_t n_samples) {
+    if (order == 2) return n_samples >= 1;
+    if (order == PM_ORDER_MAGNUS6) return n_samples >= 3 && n_samples % 3 == 0;
+    return n_samples >= 3 && n_samples % 2 == 1;
+}
+
 pm_status check_prop_args(pm_ctx* ctx, int64_t n_samples, double dt) {
     if (!ctx) return PM_E_INVALID_ARG;
     if (ctx->broken) return fail(ctx, PM_E_DEVICE, "context unusable after a device error");
     if (!ctx->ready) return fail(ctx, PM_E_NOT_READY, "pm_set_hamiltonian has not been called");
     if (!(dt > 0.0) || !std::isfinite(dt)) return fail(ctx, PM_E_INVALID_ARG, "dt must be finite and > 0");
-    if (ctx->order == 2 && n_samples < 1)
-        return fail(ctx, PM_E_INVALID_ARG, "order 2 needs n_samples >= 1");
-    if (ctx->order != 2 && (n_samples < 3 || (n_samples % 2) == 0))
-        return fail(ctx, PM_E_INVALID_ARG, "orders 4 and CF4 need an odd n_samples >= 3");
+    if (!samples_ok(ctx->order, n_samples))
+        return fail(ctx, PM_E_INVALID_ARG, ctx->order == 2 ? "order 2 needs n_samples >= 1" :
+                    ctx->order == PM_ORDER_MAGNUS6 ? "order 6 needs n_samples = 3N, N >= 1" :
+                    "orders 4 and CF4 need an odd n_samples >= 3");
     if (n_samples > (int64_t(1) << 40)) return fail(ctx, PM_E_INVALID_ARG, "n_samples too large");
     return PM_OK;
 }
@@ -658,7 +669,7 @@ const char* pm_last_error(const pm_ctx* ctx) { return ctx ? ctx->err.c_str() : g
 
 int64_t pm_basis_count(int64_t n_ctrl, int order) {
     if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl) return -1;
-    if (order == 2 || order == PM_ORDER_CF4) return 1 + n_ctrl;
+    if (order == 2 || order == PM_ORDER_CF4 || order == PM_ORDER_MAGNUS6) return 1 + n_ctrl;
     if (order == 4) return 1 + 2 * n_ctrl + n_ctrl * (n_ctrl - 1) / 2;
     return -1;
 }
@@ -726,12 +737,29 @@ pm_status pm_slice_weights_host(int64_t n_ctrl, const double* samples, int64_t n
     if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl || (n_ctrl > 0 && !samples) || !weights_out ||
         !order_ok(order))
         return PM_E_INVALID_ARG;
-    if (order != 2 && (n_samples < 3 || (n_samples % 2) == 0)) return PM_E_INVALID_ARG;
+    if (!samples_ok(order, n_samples)) return PM_E_INVALID_ARG;
     const int64_t N = n_exps_of(order, n_samples);
     if (slice < 0 || slice >= N) return PM_E_INVALID_ARG;
     const int64_t K = n_ctrl, S = n_samples;
     const double h = dt;
     int64_t m = 0;
+    if (order == PM_ORDER_MAGNUS6) {
+        // the three moments P1, P2, P3 on {H0, H_k}
+        const double r15 = std::sqrt(15.0);
+        weights_out[m++] = h;
+        for (int64_t k = 0; k < K; ++k) weights_out[m++] = h * samples[k * S + 3 * slice + 1];
+        weights_out[m++] = 0.0;
+        for (int64_t k = 0; k < K; ++k) {
+            const double* c = samples + k * S + 3 * slice;
+            weights_out[m++] = (r15 * h / 3.0) * (c[2] - c[0]);
+        }
+        weights_out[m++] = 0.0;
+        for (int64_t k = 0; k < K; ++k) {
+            const double* c = samples + k * S + 3 * slice;
+            weights_out[m++] = (10.0 * h / 3.0) * ((c[2] - 2.0 * c[1]) + c[0]);
+        }
+        return PM_OK;
+    }
     if (order == PM_ORDER_CF4) {
         // factor f of slice j: (h/12)(3 s0 + 4 s1 - s2), mirrored for f = 1
         const int64_t j = slice >> 1;
@@ -865,10 +893,16 @@ pm_status pm_set_hamiltonian(pm_ctx* ctx, int64_t dim, const double* H0, int64_t
     if (ctx->broken) return fail(ctx, PM_E_DEVICE, "context unusable after a device error");
     if (dim < 1 || dim > PM_MAX_DIM) return fail(ctx, PM_E_INVALID_ARG, "dim must be in [1, 64]");
     if (n_ctrl < 0 || n_ctrl > pm::kMaxCtrl) return fail(ctx, PM_E_INVALID_ARG, "n_ctrl must be in [0, 8]");
-    if (!order_ok(order)) return fail(ctx, PM_E_INVALID_ARG, "order must be 2, 4 or PM_ORDER_CF4");
+    if (!order_ok(order))
+        return fail(ctx, PM_E_INVALID_ARG, "order must be 2, 4, PM_ORDER_CF4 or PM_ORDER_MAGNUS6");
+    if (order == PM_ORDER_MAGNUS6 && ctx->precision != PM_FP64)
+        return fail(ctx, PM_E_UNSUPPORTED, "the sixth-order integrator runs in PM_FP64 contexts only");
     if (!H0 || (n_ctrl > 0 && !Hk)) return fail(ctx, PM_E_INVALID_ARG, "null Hamiltonian pointer");
     pm::EngineInfo e;
-    if (!pm::pick_engine((int)dim, ctx->precision, &e))
+    // the sixth-order exponent is formed by tile products: dimensions <= 4
+    // embed in the 16-wide MFMA engine
+    const int edim = order == PM_ORDER_MAGNUS6 && dim <= 4 ? 16 : (int)dim;
+    if (!pm::pick_engine(edim, ctx->precision, &e))
         return fail(ctx, PM_E_UNSUPPORTED, "no engine for this dimension / precision");
     std::vector<Mat> basis;
     std::vector<std::pair<int, int>> pairs;
@@ -925,7 +959,7 @@ pm_status pm_set_hamiltonian(pm_ctx* ctx, int64_t dim, const double* H0, int64_t
     // slice pairs: the basis in both diagonal 8 x 8 blocks of the 16-wide
     // tile, for dimensions <= 8 and at most 32 basis matrices
     dfree(ctx->d_basis_pair);
-    if (e.kind == pm::ENGINE_MFMA && e.D == 16 && dim <= 8 && M <= 32) {
+    if (e.kind == pm::ENGINE_MFMA && e.D == 16 && dim <= 8 && M <= 32 && order != PM_ORDER_MAGNUS6) {
         std::vector<double> dual((size_t)M * 16 * 16 * 2, 0.0);
         for (int m = 0; m < M; ++m)
             for (int64_t r = 0; r < dim; ++r)
@@ -1026,6 +1060,8 @@ pm_status pm_equiprop(pm_ctx* ctx, const double* samples, int64_t n_samples, dou
 pm_status check_grad_args(pm_ctx* ctx) {
     if (ctx->precision != PM_FP64)
         return fail(ctx, PM_E_UNSUPPORTED, "gradients are computed by PM_FP64 contexts");
+    if (ctx->order == PM_ORDER_MAGNUS6)
+        return fail(ctx, PM_E_UNSUPPORTED, "the sixth-order integrator has no adjoint or trajectory");
     return PM_OK;
 }
 
@@ -1055,6 +1091,8 @@ pm_status pm_trajectory_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_sa
     pm_status s = check_prop_args(ctx, n_samples, dt);
     if (s != PM_OK) return s;
     if (ctx->precision != PM_FP64) return fail(ctx, PM_E_UNSUPPORTED, "trajectories are built for PM_FP64 contexts");
+    if (ctx->order == PM_ORDER_MAGNUS6)
+        return fail(ctx, PM_E_UNSUPPORTED, "the sixth-order integrator has no adjoint or trajectory");
     if (kind != PM_TRAJ_PROPAGATORS && kind != PM_TRAJ_STATES && kind != PM_TRAJ_DENSITY)
         return fail(ctx, PM_E_INVALID_ARG, "unknown trajectory kind");
     if (kind == PM_TRAJ_STATES && (n_vec < 1 || n_vec > ctx->dim))
@@ -1319,6 +1357,8 @@ pm_status pm_batch_set(pm_batch* b, const pm_instance* inst, int64_t n_inst) {
         const std::string tag = "instance " + std::to_string(i) + ": ";
         if (q.dim < 1 || q.dim > PM_MAX_DIM) return bfail(b, PM_E_INVALID_ARG, tag + "dim must be in [1, 64]");
         if (q.n_ctrl < 0 || q.n_ctrl > pm::kMaxCtrl) return bfail(b, PM_E_INVALID_ARG, tag + "n_ctrl in [0, 8]");
+        if (q.order == PM_ORDER_MAGNUS6)
+            return bfail(b, PM_E_UNSUPPORTED, tag + "batches take orders 2, 4 and PM_ORDER_CF4");
         if (!order_ok(q.order)) return bfail(b, PM_E_INVALID_ARG, tag + "order must be 2, 4 or PM_ORDER_CF4");
         if (!q.H0 || (q.n_ctrl > 0 && (!q.Hk || !q.samples))) return bfail(b, PM_E_INVALID_ARG, tag + "null pointer");
         if (!(q.dt > 0.0) || !std::isfinite(q.dt)) return bfail(b, PM_E_INVALID_ARG, tag + "dt must be finite and > 0");

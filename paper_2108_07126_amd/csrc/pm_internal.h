@@ -14,6 +14,7 @@ constexpr int kMaxBasis = 1 + 2 * kMaxCtrl + kMaxCtrl * (kMaxCtrl - 1) / 2;  // 
 constexpr int kMaxDeg = PM_MAX_TAYLOR_DEGREE;
 constexpr int kMaxCheb = PM_MAX_CHEBYSHEV_DEGREE;
 constexpr int kOrderCF4 = PM_ORDER_CF4;   // two exponentials per slice, in product order
+constexpr int kOrderM6 = PM_ORDER_MAGNUS6; // sixth-order Magnus, three samples per slice
 constexpr int kFanIn = 8;                  // fan-in of the MFMA engines' product tree
 constexpr int kFanInLog2 = 3;
 
@@ -65,6 +66,7 @@ struct TrajParams {
 };
 
 hipError_t launch_trajectory(int D, const TrajParams& tp, hipStream_t stream);
+
 
 // Control optimisation helpers (engine_grape.hip).
 hipError_t launch_fidelity(const double* U, const double* V, int du, double* W, double* loss, hipStream_t st);

@@ -230,3 +230,45 @@ def test_chebyshev_planner_is_feasible_and_optimal(prec):
     assert s == 3 and m == min(mm for mm in th if 0.3 / 8 <= th[mm])
     with pytest.raises(pm.ParamentError):
         pm.plan_chebyshev(1.0, prec, max_degree=26)
+
+
+@pytest.mark.parametrize("d,K", [(2, 1), (5, 3), (16, 3), (8, 0)])
+def test_m6_moment_weights_and_exponent(d, K):
+    """Sixth order: the three weight rows of a slice on the basis {H0, H_k}
+    give the scheme's moments P1 = h A2, P2 = (sqrt(15) h/3)(A3 - A1),
+    P3 = (10 h/3)(A3 - 2 A2 + A1) of the oracle's Hamiltonian samples, and
+    the Hermitian form the device evaluates,
+    G = P1 + P3/12 - (i/240)[-20 P1 - P3 + R1, P2 + R2] with
+    R1 = -i[P1, P2], R2 = (i/60)[P1, 2 P3 + R1], is the oracle's exponent."""
+    m6 = pm.PM_ORDER_MAGNUS6
+    w = synth.random_system(d, K, n_slices=5, h=0.2, order=m6, tag=d * 10 + K + 600)
+    assert pm.basis_count(K, m6) == 1 + K
+    B, _ = pm.build_basis_host(w.H0, w.Hk, m6)
+    A = orc.hamiltonian_samples(w.H0, w.Hk, w.samples)
+    Gref = orc.slice_exponents(w.H0, w.Hk, w.samples, w.h, m6)
+    h, r15 = w.h, math.sqrt(15.0)
+    for j in range(w.n_slices):
+        a1, a2, a3 = A[3 * j], A[3 * j + 1], A[3 * j + 2]
+        wt = pm.slice_weights_host(w.samples, w.h, m6, j)
+        assert wt.shape == (3, 1 + K)
+        P = [np.tensordot(wt[q], B, axes=1) for q in range(3)]
+        ref = [h * a2, (r15 * h / 3) * (a3 - a1), (10 * h / 3) * (a3 - 2 * a2 + a1)]
+        for q in range(3):
+            assert np.max(np.abs(P[q] - ref[q])) < 1e-14 * max(1.0, np.max(np.abs(ref[q])))
+        comm = lambda x, y: x @ y - y @ x
+        R1 = -1j * comm(P[0], P[1])
+        R2 = (1j / 60) * comm(P[0], 2 * P[2] + R1)
+        G = P[0] + P[2] / 12 - (1j / 240) * comm(-20 * P[0] - P[2] + R1, P[1] + R2)
+        assert np.max(np.abs(G - Gref[j])) < 1e-14 * max(1.0, np.max(np.abs(Gref[j])))
+
+
+def test_m6_sample_count_rules():
+    """Order 6 takes 3N samples: the weight helper refuses other counts."""
+    m6 = pm.PM_ORDER_MAGNUS6
+    c = np.zeros((1, 7))
+    with pytest.raises(pm.ParamentError):
+        pm.slice_weights_host(c, 0.1, m6, 0)
+    assert pm.slice_weights_host(np.zeros((1, 6)), 0.1, m6, 1).shape == (3, 2)
+    with pytest.raises(pm.ParamentError):
+        pm.slice_weights_host(np.zeros((1, 6)), 0.1, m6, 2)
+    assert pm.n_slices(9, m6) == 3
