@@ -160,6 +160,28 @@ pm_status pm_equiprop_dev(pm_ctx *ctx, const double *samples_dev,
                           int64_t n_samples, double dt, double *U_out_dev,
                           void *slices_out_dev, void *stream);
 
+/* pm_equiprop_dev for callers that cannot allocate device memory: code
+ * under HIP graph capture, tight serving loops, harnesses that forbid
+ * hipMalloc.  Same arguments, results and stream semantics as
+ * pm_equiprop_dev (bitwise the same U(T) and slices), but the product
+ * tree's tickets and nodes -- the propagation's only scratch memory -- live
+ * in a fixed 64 MiB device array that the library holds on each device
+ * until the process ends, instead of the context's buffers, and no
+ * allocation of any kind is made (the context's basis, uploaded by
+ * pm_set_hamiltonian, and the caller's buffers are used as given).  A
+ * propagation whose tree needs more than the array (4 KiB per tree node at
+ * dimensions 5..16, 16 KiB at 17..32, 64 KiB at 33..64; about
+ * 2 * chains / 4 + 64 nodes at 5..16 and 2 * chains + 64 above) returns
+ * PM_E_INVALID_ARG; longer chains (pm_set_chunk) shrink the tree.  The
+ * array is shared by every call on a device and keeps the last call's
+ * contents; its tickets are cleared on `stream` (by a fill kernel) before
+ * each launch.  Calls whose work overlaps on one device (other streams,
+ * other threads, other contexts) race on the array: order them on one
+ * stream. */
+pm_status pm_equiprop_dev_noalloc(pm_ctx *ctx, const double *samples_dev,
+                                  int64_t n_samples, double dt, double *U_out_dev,
+                                  void *slices_out_dev, void *stream);
+
 /* Adjoint gradient (the paper's outlook on GRAPE-style optimal control,
  * Applications and outlook section).  For a real loss L of U(T) with
  * dL = Re Tr(W^H dU(T)) -- W is 2 dL/d conj(U), the convention of PyTorch's

@@ -45,6 +45,8 @@ SIGNATURES = {
                                    ctypes.c_void_p, ctypes.c_void_p]),
     "pm_equiprop_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
+    "pm_equiprop_dev_noalloc": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
+                                               ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pm_backward_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
                                        ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p]),
     "pm_trajectory_dev": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int64, ctypes.c_double,
@@ -301,9 +303,11 @@ class Context:
                self._h)
         return (U, sl) if return_slices else U
 
-    def equiprop_dev(self, samples_t, dt: float, U_t, slices_t=None, stream=None):
+    def equiprop_dev(self, samples_t, dt: float, U_t, slices_t=None, stream=None, noalloc: bool = False):
         """Device variant: torch tensors on the GPU; enqueued on `stream`
-        (default: torch's current stream), not synchronised."""
+        (default: torch's current stream), not synchronised.  noalloc: call
+        pm_equiprop_dev_noalloc (the tree workspace in the library's fixed
+        device array; no allocation)."""
         import torch
         assert samples_t.is_cuda and samples_t.dtype == torch.float64 and samples_t.is_contiguous()
         assert U_t.is_cuda and U_t.dtype == torch.complex128 and U_t.is_contiguous()
@@ -313,7 +317,8 @@ class Context:
         if stream is None:
             stream = torch.cuda.current_stream(U_t.device)
         S = samples_t.shape[-1]
-        _check(_lib.pm_equiprop_dev(self._h, ctypes.c_void_p(samples_t.data_ptr()), S, float(dt),
+        fn = _lib.pm_equiprop_dev_noalloc if noalloc else _lib.pm_equiprop_dev
+        _check(fn(self._h, ctypes.c_void_p(samples_t.data_ptr()), S, float(dt),
                                     ctypes.c_void_p(U_t.data_ptr()),
                                     ctypes.c_void_p(slices_t.data_ptr()) if slices_t is not None else None,
                                     ctypes.c_void_p(stream.cuda_stream)), self._h)

@@ -15,7 +15,7 @@ HERE = os.path.dirname(os.path.abspath(__file__))
 CSRC = os.path.join(HERE, "csrc")
 LIB = os.path.join(HERE, "libparament.so")
 SOURCES = ["parament.cpp", "engine_mfma.hip", "engine_mfma_pair.hip", "engine_mfma_m6.hip", "engine_valu.hip", "engine_valu_f64_2.hip", "engine_valu_f64_4.hip",
-           "engine_valu_f32_2.hip", "engine_valu_f32_4.hip", "engine_grad.hip", "engine_batch.hip", "engine_grape.hip"]
+           "engine_valu_f32_2.hip", "engine_valu_f32_4.hip", "engine_grad.hip", "engine_batch.hip", "engine_grape.hip", "noalloc.hip"]
 
 HIPCC = os.environ.get("HIPCC", "/opt/rocm/bin/hipcc")
 FLAGS = [

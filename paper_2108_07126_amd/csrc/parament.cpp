@@ -459,19 +459,45 @@ int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, b
 }
 
 // Workspace and kernel parameters of one propagation on engine e.
+// A caller-provided device workspace for the tree's tickets and nodes
+// (the entry point that allocates nothing): tickets first, 256-byte aligned,
+// then the nodes.
+struct FixedWorkspace {
+    void* base;
+    size_t bytes;
+};
+
+size_t round256(size_t x) { return (x + 255) & ~(size_t)255; }
+
 pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, bool keep_nodes, const double* basis, const double* d_samples,
-                  int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out) {
+                  int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out,
+                  const FixedWorkspace* fixed = nullptr) {
     const int64_t N = n_exps_of(ctx->order, n_samples);
     const int64_t chunk = effective_chunk(ctx, e, N, keep_nodes, d_slices != nullptr);
     const int64_t chains = (N + chunk - 1) / chunk;
     const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
     const size_t node_bytes = (size_t)e.D * e.D * 16;
-    pm_status st = ensure(ctx, (void**)&ctx->d_nodes, &ctx->nodes_bytes,
-                          node_bytes * (size_t)(2 * leaves + 64), "tree nodes");
-    if (st != PM_OK) return st;
-    st = ensure(ctx, (void**)&ctx->d_counters, &ctx->counters_bytes,
-                sizeof(unsigned) * (size_t)(2 * leaves + 64), "tree tickets", true);
-    if (st != PM_OK) return st;
+    const size_t nodes_need = node_bytes * (size_t)(2 * leaves + 64);
+    const size_t tickets_need = sizeof(unsigned) * (size_t)(2 * leaves + 64);
+    double* nodes;
+    unsigned* tickets;
+    if (fixed) {
+        const size_t need = round256(tickets_need) + nodes_need;
+        if (need > fixed->bytes)
+            return fail(ctx, PM_E_INVALID_ARG,
+                        "this propagation needs " + std::to_string(need) + " bytes of tree workspace (" +
+                            std::to_string(leaves) + " leaves); the fixed workspace holds " +
+                            std::to_string(fixed->bytes) + " (use longer chains: pm_set_chunk)");
+        tickets = static_cast<unsigned*>(fixed->base);
+        nodes = reinterpret_cast<double*>(static_cast<char*>(fixed->base) + round256(tickets_need));
+    } else {
+        pm_status st = ensure(ctx, (void**)&ctx->d_nodes, &ctx->nodes_bytes, nodes_need, "tree nodes");
+        if (st != PM_OK) return st;
+        st = ensure(ctx, (void**)&ctx->d_counters, &ctx->counters_bytes, tickets_need, "tree tickets", true);
+        if (st != PM_OK) return st;
+        nodes = ctx->d_nodes;
+        tickets = ctx->d_counters;
+    }
 
     pm::PropParams& p = *out;
     std::memset(&p, 0, sizeof(p));
@@ -483,8 +509,8 @@ pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, bool keep_nodes, const d
     p.n_chains = chains;
     p.n_leaves = leaves;
     p.slices_out = d_slices;
-    p.nodes = ctx->d_nodes;
-    p.counters = ctx->d_counters;
+    p.nodes = nodes;
+    p.counters = tickets;
     p.U_out = d_U;
     p.h = dt;
     if (ctx->theta_n != N) {
@@ -1012,6 +1038,47 @@ pm_status pm_equiprop_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samp
     if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
     return launch(ctx, samples_dev, n_samples, dt, U_out_dev, slices_out_dev, (hipStream_t)stream);
 }
+
+}  // extern "C"
+
+namespace pm {
+
+// pm_equiprop_dev with the tree's tickets and nodes in a fixed device
+// workspace [base, base + bytes) instead of the context's buffers; nothing
+// is allocated.  The tickets are cleared on the stream by a fill kernel
+// before the launch.
+pm_status equiprop_fixed_workspace(pm_ctx* ctx, const double* samples_dev, int64_t n_samples, double dt,
+                                   double* U_out_dev, void* slices_out_dev, void* stream, void* base,
+                                   size_t bytes) {
+    pm_status s = check_prop_args(ctx, n_samples, dt);
+    if (s != PM_OK) return s;
+    if (!U_out_dev) return fail(ctx, PM_E_INVALID_ARG, "U_out is null");
+    if (ctx->n_ctrl > 0 && !samples_dev) return fail(ctx, PM_E_INVALID_ARG, "samples is null");
+    if (slices_out_dev && ctx->order == PM_ORDER_CF4)
+        return fail(ctx, PM_E_INVALID_ARG, "per-slice output is not available with PM_ORDER_CF4");
+    DeviceGuard g(ctx->device);
+    if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    PropParams p;
+    const FixedWorkspace fw{base, bytes};
+    s = prepare(ctx, ctx->eng, false, ctx->d_basis, samples_dev, n_samples, dt, U_out_dev, slices_out_dev, &p,
+                &fw);
+    if (s != PM_OK) return s;
+    const hipStream_t st = (hipStream_t)stream;
+    const int64_t words = 2 * p.n_leaves + 64;
+    hipError_t he = launch_zero(reinterpret_cast<double*>(p.counters), (words + 1) / 2, st);
+    if (he != hipSuccess) return hip_fail(ctx, he, "ticket clear");
+    he = launch_propagate(ctx->eng, ctx->precision, p, st);
+    if (he != hipSuccess) return hip_fail(ctx, he, "kernel launch");
+    return PM_OK;
+}
+
+int context_device(const pm_ctx* ctx) { return ctx ? ctx->device : -1; }
+
+pm_status context_device_fail(pm_ctx* ctx, hipError_t e, const char* where) { return hip_fail(ctx, e, where); }
+
+}  // namespace pm
+
+extern "C" {
 
 pm_status pm_equiprop(pm_ctx* ctx, const double* samples, int64_t n_samples, double dt,
                       double* U_out, void* slices_out) {

@@ -67,6 +67,14 @@ struct TrajParams {
 
 hipError_t launch_trajectory(int D, const TrajParams& tp, hipStream_t stream);
 
+// Propagation with the tree workspace in a caller-provided device region
+// (parament.cpp; used by the entry point that allocates nothing).
+pm_status equiprop_fixed_workspace(pm_ctx* ctx, const double* samples_dev, int64_t n_samples, double dt,
+                                   double* U_out_dev, void* slices_out_dev, void* stream, void* base,
+                                   size_t bytes);
+int context_device(const pm_ctx* ctx);
+pm_status context_device_fail(pm_ctx* ctx, hipError_t e, const char* where);
+
 
 // Control optimisation helpers (engine_grape.hip).
 hipError_t launch_fidelity(const double* U, const double* V, int du, double* W, double* loss, hipStream_t st);
