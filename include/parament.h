@@ -320,6 +320,48 @@ pm_status pm_tuning_set(const char *key, int dim_class, int precision, int64_t v
 pm_status pm_set_expm_policy(pm_ctx *ctx, int max_taylor_degree, int force_s);
 pm_status pm_set_chunk(pm_ctx *ctx, int64_t chunk);
 
+/* ---- device workspace ---------------------------------------------------
+ * Besides the basis uploaded by pm_set_hamiltonian, a context allocates
+ * per-call workspace on its device and keeps it for the next call: the
+ * product tree's nodes and tickets; for the gradient and the trajectory the
+ * checkpoints (U(T) and one product per chain of slices) and, for the
+ * gradient, the weight gradients of every slice (N x basis count doubles);
+ * the host-buffer entry points also stage their inputs and outputs there.
+ * Kinds of call for pm_workspace_plan: */
+typedef enum pm_work_kind {
+    PM_WORK_PROPAGATE = 0,    /* pm_equiprop_dev returning U(T) (per-slice output in the caller's buffer) */
+    PM_WORK_GRADIENT = 1,     /* pm_backward_dev                                                          */
+    PM_WORK_TRAJECTORY = 2    /* pm_trajectory_dev                                                        */
+} pm_work_kind;
+
+/* Limit the context's device workspace to `bytes` (0: no limit, the
+ * default).  Every later call plans its chain length so that its workspace
+ * fits: the automatic length is doubled until it does -- fewer tree nodes
+ * and, for the gradient and the trajectory, checkpoints further apart
+ * (each chain's slices are recomputed from its checkpoint, so memory is
+ * traded for recomputation: the checkpoint interval grows as the limit
+ * shrinks).  A call whose workspace cannot fit even as a single chain, or
+ * at a chain length fixed by pm_set_chunk, returns PM_E_OOM before
+ * allocating anything.  Before a call the context releases what it holds
+ * from earlier calls if that plus the call's need would pass the limit.
+ * Setting a limit below what is held releases it now (synchronising the
+ * device).  The fixed-workspace entry point pm_equiprop_dev_noalloc does
+ * not use the context's workspace. */
+pm_status pm_set_workspace_limit(pm_ctx *ctx, int64_t bytes);
+
+/* Bytes of device workspace the context holds now (-1 for NULL). */
+int64_t pm_workspace_held(const pm_ctx *ctx);
+
+/* Host-only: the chain length (*chunk_out) and device workspace in bytes
+ * (*bytes_out, may be NULL) a call of `kind` with n_samples samples would
+ * use on a context of this dimension, control count, order and precision
+ * with no chunk override, under the workspace limit `limit` (0: none);
+ * PM_E_OOM if it cannot fit, PM_E_UNSUPPORTED for a kind or order the
+ * precision does not take.  No GPU is touched. */
+pm_status pm_workspace_plan(int64_t dim, int64_t n_ctrl, int order, int precision,
+                            int64_t n_samples, int kind, int64_t limit, int64_t *chunk_out,
+                            int64_t *bytes_out);
+
 /* Choose the exponential (pm_expm_method) for pm_equiprop / pm_equiprop_dev.
  * PM_EXPM_CHEBYSHEV: per slice, with nu = ||G_j||_1 (the spectrum lies in
  * [-nu, nu]), the planner picks the degree m <= PM_MAX_CHEBYSHEV_DEGREE and
@@ -400,10 +442,6 @@ pm_status pm_slice_weights_host(int64_t n_ctrl, const double *samples,
  * n_slices >= 1. */
 pm_status pm_taylor_theta(int m, int precision, int64_t n_slices, double *theta_out);
 
-/* The planner's choice for a slice with ||G||_1 = nu in a propagation of
- * n_slices slices: Taylor degree m and squarings s minimising the product
- * count (ties to the smaller s), subject to nu / 2^s <= theta_m and
- * m <= max_degree. */
 /* Table 1 of the paper: the largest ||G|| for which the degree-m Chebyshev
  * series meets Lubich's estimate (eq. error_chebychev)
  *     4 (exp(1 - rho^2) rho)^(m+1) <= u,   rho = 2 ||G|| / (4m + 4),
@@ -416,6 +454,10 @@ pm_status pm_chebyshev_theta(int m, int precision, double *theta_out);
 pm_status pm_plan_chebyshev(double nu, int precision, int max_degree, int force_s, int *m_out,
                             int *s_out);
 
+/* The planner's choice for a slice with ||G||_1 = nu in a propagation of
+ * n_slices slices: Taylor degree m and squarings s minimising the product
+ * count (ties to the smaller s), subject to nu / 2^s <= theta_m and
+ * m <= max_degree. */
 pm_status pm_plan_expm(double nu, int precision, int max_degree, int64_t n_slices,
                        int *m_out, int *s_out);
 

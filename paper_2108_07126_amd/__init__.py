@@ -24,6 +24,7 @@ PM_FP64, PM_FP32, PM_FP32_3M, PM_BF16_SPLIT = 0, 1, 2, 3
 PM_EXPM_TAYLOR, PM_EXPM_CHEBYSHEV = 0, 1
 PM_TRAJ_PROPAGATORS, PM_TRAJ_STATES, PM_TRAJ_DENSITY = 0, 1, 2
 PM_OPT_GD, PM_OPT_ADAM = 0, 1
+PM_WORK_PROPAGATE, PM_WORK_GRADIENT, PM_WORK_TRAJECTORY = 0, 1, 2
 PM_ORDER_MIDPOINT, PM_ORDER_MAGNUS4, PM_ORDER_CF4, PM_ORDER_MAGNUS6 = 2, 4, 5, 6
 MAX_CHEBYSHEV_DEGREE = 25
 PRECISIONS = {"fp64": PM_FP64, "fp32": PM_FP32, "fp32_3m": PM_FP32_3M, "bf16_split": PM_BF16_SPLIT}
@@ -34,6 +35,7 @@ MAX_TAYLOR_DEGREE = 21
 
 _c_double_p = ctypes.POINTER(ctypes.c_double)
 _c_int_p = ctypes.POINTER(ctypes.c_int)
+_c_i64_p = ctypes.POINTER(ctypes.c_int64)
 
 # name -> (restype, argtypes): every entry point declared in include/parament.h
 SIGNATURES = {
@@ -86,6 +88,10 @@ SIGNATURES = {
     "pm_taylor_theta": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, ctypes.c_int64, _c_double_p]),
     "pm_plan_expm": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int64, _c_int_p,
                                     _c_int_p]),
+    "pm_set_workspace_limit": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "pm_workspace_held": (ctypes.c_int64, [ctypes.c_void_p]),
+    "pm_workspace_plan": (ctypes.c_int, [ctypes.c_int64, ctypes.c_int64, ctypes.c_int, ctypes.c_int, ctypes.c_int64,
+                                         ctypes.c_int, ctypes.c_int64, _c_i64_p, _c_i64_p]),
 }
 
 
@@ -213,6 +219,16 @@ def plan_chebyshev(nu: float, precision: int = PM_FP64, max_degree: int = MAX_CH
     return m.value, s.value
 
 
+def workspace_plan(dim: int, n_ctrl: int, order: int, precision: int, n_samples: int,
+                   kind: int = PM_WORK_PROPAGATE, limit: int = 0) -> Tuple[int, int]:
+    """(chain length, device workspace bytes) of a call under a workspace
+    limit (host-only; raises ParamentError PM_E_OOM if it cannot fit)."""
+    c, b = ctypes.c_int64(), ctypes.c_int64()
+    _check(_lib.pm_workspace_plan(dim, n_ctrl, order, precision, n_samples, kind, int(limit),
+                                  ctypes.byref(c), ctypes.byref(b)))
+    return c.value, b.value
+
+
 def n_slices(n_samples: int, order: int) -> int:
     """Slices covered by n_samples samples (2N + 1 samples for order 4 and
     CF4, 3N for order 6)."""
@@ -280,6 +296,15 @@ class Context:
     def set_expm_method(self, method: int = PM_EXPM_TAYLOR):
         """PM_EXPM_TAYLOR (default) or PM_EXPM_CHEBYSHEV (the paper's series)."""
         _check(_lib.pm_set_expm_method(self._h, method), self._h)
+
+    def set_workspace_limit(self, nbytes: int = 0):
+        """Limit the context's device workspace (0: no limit)."""
+        _check(_lib.pm_set_workspace_limit(self._h, int(nbytes)), self._h)
+
+    @property
+    def workspace_held(self) -> int:
+        """Bytes of device workspace the context holds now."""
+        return int(_lib.pm_workspace_held(self._h))
 
     def launch_shape(self, n_samples: int) -> Tuple[int, int, int]:
         """(chunk, chains, leaves) a propagation of n_samples would use."""

@@ -45,6 +45,8 @@ struct pm_ctx {
     int max_degree = PM_MAX_TAYLOR_DEGREE;
     int force_s = -1;
     int64_t chunk_override = 0;
+    int64_t call_chunk = 0;      // chain length planned for the current call (0: none)
+    int64_t ws_limit = 0;        // device workspace limit in bytes (0: none)
     int method = PM_EXPM_TAYLOR;
     double* d_cheb = nullptr;    // Chebyshev coefficient table on the device
     // device buffers
@@ -449,6 +451,7 @@ int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool keep_
 // addresses a chain's slices with 32-bit offsets).
 int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, bool keep_nodes = false,
                         bool per_slice = false) {
+    if (ctx->call_chunk > 0) return ctx->call_chunk;
     int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override
                                         : auto_chunk(e, N, ctx->precision, keep_nodes, per_slice);
     c = ((c + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
@@ -456,6 +459,111 @@ int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, b
     // CF4: a chain starts at a slice boundary (an even exponential index)
     if (ctx->order == PM_ORDER_CF4 && (c & 1)) ++c;
     return c;
+}
+
+// ---- device workspace under the context's limit (pm_set_workspace_limit)
+
+// Bytes ensure() allocates for a request.
+size_t alloc_bytes(size_t need) { return std::max<size_t>(need, 256); }
+
+// The context's device workspace for one call at chain length `chunk`:
+// the product tree's nodes and tickets; for the checkpointed forward pass
+// (gradient, trajectory) also U(T) and every chain product; for the
+// gradient the weight gradients of every slice.
+size_t call_bytes(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, int64_t chunk, int kind) {
+    const int64_t chains = (N + chunk - 1) / chunk;
+    const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
+    const size_t node = (size_t)e.D * e.D * 16;
+    size_t b = alloc_bytes(node * (size_t)(2 * leaves + 64)) + alloc_bytes(4 * (size_t)(2 * leaves + 64));
+    if (kind != PM_WORK_PROPAGATE) b += 16 * PM_MAX_DIM * PM_MAX_DIM + alloc_bytes(node * (size_t)chains);
+    if (kind == PM_WORK_GRADIENT) b += alloc_bytes(sizeof(double) * (size_t)N * ctx->M);
+    return b;
+}
+
+// Chain length of a call of `kind` over N exponentials with `extra` bytes
+// of other workspace: the automatic (or pm_set_chunk's) length, doubled
+// while the call's workspace exceeds the limit -- longer chains mean fewer
+// tree nodes and, for the gradient and the trajectory, checkpoints further
+// apart with more recomputation between them.  PM_E_OOM when even one chain
+// does not fit, or when the length fixed by pm_set_chunk does not.
+pm_status plan_call(pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, int kind, bool per_slice, size_t extra,
+                    int64_t* chunk_out, size_t* bytes_out) {
+    const bool keep = kind != PM_WORK_PROPAGATE;
+    int64_t c = effective_chunk(ctx, e, N, keep, per_slice);
+    size_t b = call_bytes(ctx, e, N, c, kind) + extra;
+    const size_t lim = (size_t)ctx->ws_limit;
+    if (ctx->ws_limit > 0 && b > lim) {
+        if (ctx->chunk_override > 0)
+            return fail(ctx, PM_E_OOM, "the chain length set by pm_set_chunk needs " + std::to_string(b) +
+                                           " bytes of device workspace, over the limit of " + std::to_string(lim));
+        const int64_t u = e.chunk_unit;
+        const int64_t cmax = e.kind == pm::ENGINE_VALU ? std::min<int64_t>(N, int64_t(1) << 20) : N;
+        while (b > lim && c < cmax) {
+            c = std::min<int64_t>(2 * c, ((cmax + u - 1) / u) * u);
+            c = ((c + u - 1) / u) * u;
+            if (e.kind == pm::ENGINE_VALU && c > (int64_t(1) << 20)) c = int64_t(1) << 20;
+            if (ctx->order == PM_ORDER_CF4 && (c & 1)) ++c;
+            b = call_bytes(ctx, e, N, c, kind) + extra;
+        }
+        if (b > lim)
+            return fail(ctx, PM_E_OOM, "this call needs at least " + std::to_string(b) +
+                                           " bytes of device workspace, over the limit of " + std::to_string(lim));
+    }
+    *chunk_out = c;
+    if (bytes_out) *bytes_out = b;
+    return PM_OK;
+}
+
+// Device workspace the context holds (every per-call buffer; not the basis
+// or the Chebyshev table uploaded at set-up).
+size_t held_workspace(const pm_ctx* c) {
+    return c->nodes_bytes + c->counters_bytes + c->samples_bytes + c->u_bytes + c->slices_bytes + c->chain_bytes +
+           c->gw_bytes + c->ut_bytes + c->w_bytes + c->grad_bytes + c->mom_bytes;
+}
+
+pm_status release_workspace(pm_ctx* c) {
+    DeviceGuard g(c->device);
+    const hipError_t e = hipDeviceSynchronize();
+    if (e != hipSuccess) return hip_fail(c, e, "hipDeviceSynchronize");
+    dfree(c->d_nodes);
+    dfree(c->d_counters);
+    dfree(c->d_samples);
+    dfree(c->d_U);
+    dfree(c->d_chain);
+    dfree(c->d_gw);
+    dfree(c->d_UT);
+    dfree(c->d_W);
+    dfree(c->d_grad);
+    dfree(c->d_mom);
+    if (c->d_slices) (void)hipFree(c->d_slices);
+    c->d_slices = nullptr;
+    c->nodes_bytes = c->counters_bytes = c->samples_bytes = c->u_bytes = c->slices_bytes = 0;
+    c->chain_bytes = c->gw_bytes = c->ut_bytes = c->w_bytes = c->grad_bytes = c->mom_bytes = 0;
+    return PM_OK;
+}
+
+// Before a call that needs `need` bytes: if what the context holds plus
+// that could pass the limit, release the held buffers first, so the call
+// allocates no more than its own need.
+pm_status fit_workspace(pm_ctx* ctx, size_t need) {
+    if (ctx->ws_limit <= 0 || held_workspace(ctx) + need <= (size_t)ctx->ws_limit) return PM_OK;
+    return release_workspace(ctx);
+}
+
+// The planned chain length, in force for the duration of one entry point.
+struct CallChunk {
+    pm_ctx* c;
+    CallChunk(pm_ctx* ctx, int64_t chunk) : c(ctx) { c->call_chunk = chunk; }
+    ~CallChunk() { c->call_chunk = 0; }
+};
+
+// Plan, fit and fix the chain length of one call.
+pm_status begin_call(pm_ctx* ctx, const pm::EngineInfo& e, int64_t n_samples, int kind, bool per_slice,
+                     size_t extra, int64_t* chunk) {
+    size_t need = 0;
+    pm_status s = plan_call(ctx, e, n_exps_of(ctx->order, n_samples), kind, per_slice, extra, chunk, &need);
+    if (s != PM_OK) return s;
+    return fit_workspace(ctx, need);
 }
 
 // Workspace and kernel parameters of one propagation on engine e.
@@ -870,6 +978,43 @@ pm_status pm_set_chunk(pm_ctx* ctx, int64_t chunk) {
     return PM_OK;
 }
 
+pm_status pm_set_workspace_limit(pm_ctx* ctx, int64_t bytes) {
+    if (!ctx) return PM_E_INVALID_ARG;
+    if (bytes < 0) return fail(ctx, PM_E_INVALID_ARG, "the workspace limit must be >= 0");
+    ctx->ws_limit = bytes;
+    if (bytes > 0 && held_workspace(ctx) > (size_t)bytes) return release_workspace(ctx);
+    return PM_OK;
+}
+
+int64_t pm_workspace_held(const pm_ctx* ctx) { return ctx ? (int64_t)held_workspace(ctx) : -1; }
+
+pm_status pm_workspace_plan(int64_t dim, int64_t n_ctrl, int order, int precision, int64_t n_samples, int kind,
+                            int64_t limit, int64_t* chunk_out, int64_t* bytes_out) {
+    if (dim < 1 || dim > PM_MAX_DIM || n_ctrl < 0 || n_ctrl > pm::kMaxCtrl || !order_ok(order) || limit < 0 ||
+        !chunk_out || !samples_ok(order, n_samples) || unit_roundoff(precision) < 0 ||
+        (kind != PM_WORK_PROPAGATE && kind != PM_WORK_GRADIENT && kind != PM_WORK_TRAJECTORY))
+        return PM_E_INVALID_ARG;
+    if ((order == PM_ORDER_MAGNUS6 || kind != PM_WORK_PROPAGATE) && precision != PM_FP64) return PM_E_UNSUPPORTED;
+    if (order == PM_ORDER_MAGNUS6 && kind != PM_WORK_PROPAGATE) return PM_E_UNSUPPORTED;
+    // a context as pm_set_hamiltonian would leave it, without the device
+    pm_ctx c;
+    c.precision = precision;
+    c.dim = dim;
+    c.n_ctrl = n_ctrl;
+    c.order = order;
+    c.M = (int)pm_basis_count(n_ctrl, order);
+    c.ws_limit = limit;
+    const int edim = order == PM_ORDER_MAGNUS6 && dim <= 4 ? 16 : (int)dim;
+    if (!pm::pick_engine(edim, precision, &c.eng) || !pm::pick_engine(dim <= 16 ? 16 : (int)dim, PM_FP64, &c.geng))
+        return PM_E_UNSUPPORTED;
+    const pm::EngineInfo& e = kind == PM_WORK_PROPAGATE ? c.eng : c.geng;
+    size_t b = 0;
+    const pm_status s = plan_call(&c, e, n_exps_of(order, n_samples), kind, false, 0, chunk_out, &b);
+    if (s != PM_OK) return s;
+    if (bytes_out) *bytes_out = (int64_t)b;
+    return PM_OK;
+}
+
 pm_status pm_set_expm_method(pm_ctx* ctx, int method) {
     if (!ctx) return PM_E_INVALID_ARG;
     if (method != PM_EXPM_TAYLOR && method != PM_EXPM_CHEBYSHEV)
@@ -905,8 +1050,11 @@ pm_status pm_launch_shape(pm_ctx* ctx, int64_t n_samples, int64_t* chunk, int64_
     if (!ctx || !chunk || !chains || !leaves) return ctx ? fail(ctx, PM_E_INVALID_ARG, "null output") : PM_E_INVALID_ARG;
     if (ctx->dim == 0) return fail(ctx, PM_E_NOT_READY, "pm_set_hamiltonian has not been called");
     const int64_t N = n_exps_of(ctx->order, n_samples);
-    if (N < 1) return fail(ctx, PM_E_INVALID_ARG, "bad n_samples for the integrator order");
-    const int64_t c = effective_chunk(ctx, ctx->eng, N);
+    if (N < 1 || !samples_ok(ctx->order, n_samples))
+        return fail(ctx, PM_E_INVALID_ARG, "bad n_samples for the integrator order");
+    int64_t c = 0;
+    const pm_status s = plan_call(ctx, ctx->eng, N, PM_WORK_PROPAGATE, false, 0, &c, nullptr);
+    if (s != PM_OK) return s;
     *chunk = c;
     *chains = (N + c - 1) / c;
     *leaves = (*chains + ctx->eng.chains_per_leaf - 1) / ctx->eng.chains_per_leaf;
@@ -1036,6 +1184,10 @@ pm_status pm_equiprop_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samp
         return fail(ctx, PM_E_INVALID_ARG, "per-slice output is not available with PM_ORDER_CF4");
     DeviceGuard g(ctx->device);
     if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    int64_t chunk = 0;
+    s = begin_call(ctx, ctx->eng, n_samples, PM_WORK_PROPAGATE, slices_out_dev != nullptr, 0, &chunk);
+    if (s != PM_OK) return s;
+    CallChunk cc(ctx, chunk);
     return launch(ctx, samples_dev, n_samples, dt, U_out_dev, slices_out_dev, (hipStream_t)stream);
 }
 
@@ -1095,12 +1247,18 @@ pm_status pm_equiprop(pm_ctx* ctx, const double* samples, int64_t n_samples, dou
     if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
     const int64_t N = n_slices_of(ctx->order, n_samples);
     const size_t sbytes = sizeof(double) * (size_t)std::max<int64_t>(K * n_samples, 1);
+    const size_t elem = ctx->precision == PM_FP64 ? 16 : 8;
+    const size_t slbytes = elem * (size_t)N * ctx->dim * ctx->dim;
+    int64_t chunk = 0;
+    s = begin_call(ctx, ctx->eng, n_samples, PM_WORK_PROPAGATE, slices_out != nullptr,
+                   alloc_bytes(sbytes) + 16 * PM_MAX_DIM * PM_MAX_DIM + (slices_out ? alloc_bytes(slbytes) : 0),
+                   &chunk);
+    if (s != PM_OK) return s;
+    CallChunk cc(ctx, chunk);
     s = ensure(ctx, (void**)&ctx->d_samples, &ctx->samples_bytes, sbytes, "samples");
     if (s != PM_OK) return s;
     s = ensure(ctx, (void**)&ctx->d_U, &ctx->u_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "U");
     if (s != PM_OK) return s;
-    const size_t elem = ctx->precision == PM_FP64 ? 16 : 8;
-    const size_t slbytes = elem * (size_t)N * ctx->dim * ctx->dim;
     if (slices_out) {
         s = ensure(ctx, &ctx->d_slices, &ctx->slices_bytes, slbytes, "slices");
         if (s != PM_OK) return s;
@@ -1142,6 +1300,10 @@ pm_status pm_backward_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samp
         return fail(ctx, PM_E_INVALID_ARG, "null pointer");
     DeviceGuard g(ctx->device);
     if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    int64_t chunk = 0;
+    s = begin_call(ctx, ctx->geng, n_samples, PM_WORK_GRADIENT, false, 0, &chunk);
+    if (s != PM_OK) return s;
+    CallChunk cc(ctx, chunk);
     hipStream_t st = (hipStream_t)stream;
     s = launch_grad(ctx, samples_dev, n_samples, dt, W_dev, grad_dev, st, true, true);
     if (s != PM_OK) return s;
@@ -1168,6 +1330,10 @@ pm_status pm_trajectory_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_sa
         return fail(ctx, PM_E_INVALID_ARG, "null pointer");
     DeviceGuard g(ctx->device);
     if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    int64_t chunk = 0;
+    s = begin_call(ctx, ctx->geng, n_samples, PM_WORK_TRAJECTORY, false, 0, &chunk);
+    if (s != PM_OK) return s;
+    CallChunk cc(ctx, chunk);
     hipStream_t st = (hipStream_t)stream;
     pm::TrajParams tp;
     s = forward_keep(ctx, samples_dev, n_samples, dt, st, true, &tp.p);
@@ -1194,6 +1360,13 @@ pm_status pm_grape_dev(pm_ctx* ctx, double* samples_dev, int64_t n_samples, doub
     if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
     hipStream_t st = (hipStream_t)stream;
     const int64_t n = ctx->n_ctrl * n_samples;
+    int64_t chunk = 0;
+    s = begin_call(ctx, ctx->geng, n_samples, PM_WORK_GRADIENT, false,
+                   16 * PM_MAX_DIM * PM_MAX_DIM + alloc_bytes(sizeof(double) * (size_t)std::max<int64_t>(n, 1)) +
+                       alloc_bytes(sizeof(double) * (size_t)std::max<int64_t>(2 * n, 1)),
+                   &chunk);
+    if (s != PM_OK) return s;
+    CallChunk cc(ctx, chunk);
     s = ensure(ctx, (void**)&ctx->d_W, &ctx->w_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "W");
     if (s != PM_OK) return s;
     s = ensure(ctx, (void**)&ctx->d_grad, &ctx->grad_bytes, sizeof(double) * (size_t)std::max<int64_t>(n, 1),
@@ -1234,6 +1407,12 @@ pm_status pm_fidelity_grad(pm_ctx* ctx, const double* samples, int64_t n_samples
         if (!std::isfinite(samples[i])) return fail(ctx, PM_E_INVALID_ARG, "non-finite control sample");
     DeviceGuard g(ctx->device);
     if (!g.ok) return hip_fail(ctx, hipErrorInvalidDevice, "hipSetDevice");
+    const size_t kb = alloc_bytes(sizeof(double) * (size_t)std::max<int64_t>(K * n_samples, 1));
+    int64_t chunk = 0;
+    s = begin_call(ctx, ctx->geng, n_samples, PM_WORK_GRADIENT, false, 2 * kb + 16 * PM_MAX_DIM * PM_MAX_DIM,
+                   &chunk);
+    if (s != PM_OK) return s;
+    CallChunk cc(ctx, chunk);
     s = ensure(ctx, (void**)&ctx->d_samples, &ctx->samples_bytes,
                sizeof(double) * (size_t)std::max<int64_t>(K * n_samples, 1), "samples");
     if (s != PM_OK) return s;

@@ -75,7 +75,6 @@ pm_status equiprop_fixed_workspace(pm_ctx* ctx, const double* samples_dev, int64
 int context_device(const pm_ctx* ctx);
 pm_status context_device_fail(pm_ctx* ctx, hipError_t e, const char* where);
 
-
 // Control optimisation helpers (engine_grape.hip).
 hipError_t launch_fidelity(const double* U, const double* V, int du, double* W, double* loss, hipStream_t st);
 hipError_t launch_update(double* c, const double* g, double* m, double* v, int64_t n, double step, int optimizer,
