@@ -18,9 +18,11 @@
 // a lane is the B operand of k-slice r, and the A operand of a Hermitian
 // left factor (or of U = C - i P) is formed from the lane's own registers.
 // Larger teams stage both operands in LDS (row stride D+1, split re/im
-// planes, conflict-free fragment reads).  Complex products run as three real
-// MFMA products (3M) in FP64, FP32-3M and BF16 split, four in plain FP32
-// (v_mfma_f64_16x16x4f64, v_mfma_f32_16x16x4f32, v_mfma_f32_16x16x16_bf16).
+// planes, conflict-free fragment reads; in BF16-split mode bf16 hi/lo planes
+// split once at staging).  Complex products run as three real MFMA products
+// (3M) in FP64 and FP32-3M, four in plain FP32 and in BF16 split, each of
+// the latter's real products three split terms (v_mfma_f64_16x16x4f64,
+// v_mfma_f32_16x16x4f32, v_mfma_f32_16x16x32_bf16).
 // Finally the blocks' chain products enter the ticketed FP64 product tree of
 // mfma_tree.h (fan-in 8: the last of eight consecutive nodes to arrive
 // multiplies them, a group of one moves up unchanged) -- the reduction of the
@@ -162,7 +164,9 @@ propagate_mfma(PropParams p) {
             const double* bb = bas + bofs;
             constexpr int64_t STR = G::TW * 512;
             int m = 0;
-            for (; m + 4 <= p.M; m += 4) {
+            // (one-wave teams only: a 16-wave team's 128 registers per lane
+            // would spill the four matrices' entries)
+            for (; G::TW == 1 && m + 4 <= p.M; m += 4) {
                 double x[4][8];
 #pragma unroll
                 for (int q = 0; q < 4; ++q)

@@ -190,7 +190,7 @@ __device__ __forceinline__ Tile<T> slot_mul4(const double* A, const double* B, c
     V acc_re = {0, 0, 0, 0}, acc_im = {0, 0, 0, 0};
     const int arow = (16 * L.TI + L.j) * G::LD;
     const int bcol = 16 * L.TJ + L.j;
-#pragma unroll
+#pragma unroll 4
     for (int kb = 0; kb < G::D / 4; ++kb) {
         const int k = 4 * kb + L.g;
         const T ar = Are[arow + k], ai = Aim[arow + k];
@@ -224,7 +224,7 @@ __device__ __forceinline__ Tile<T> slot_mul_3m(const double* A, const double* B,
     V t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
     const int arow = (16 * L.TI + L.j) * G::LD;
     const int bcol = 16 * L.TJ + L.j;
-#pragma unroll
+#pragma unroll 4
     for (int kb = 0; kb < G::D / 4; ++kb) {
         const int k = 4 * kb + L.g;
         const T ar = Are[arow + k], ai = Aim[arow + k];
@@ -249,72 +249,176 @@ __device__ __forceinline__ Tile<T> slot_mul(const double* A, const double* B, co
     else return slot_mul4<G, T>(A, B, L);
 }
 
-typedef short s4_t __attribute__((ext_vector_type(4)));
+// ---- BF16 split products (the BF16-split mode) ------------------------------
+// Every operand entry x is carried as x = hi + lo, hi = bf16(x), lo =
+// bf16(x - hi) (round to nearest even), and each real product as
+// hi*hi + hi*lo + lo*hi (lo*lo lies below the FP32 rounding of the result's
+// scale), accumulated in FP32 on gfx950's 16x16x32 BF16 MFMA.  That
+// instruction takes eight BF16 values of A and of B per lane and sums, over
+// every lane group and slot, the products of the A and B values in the same
+// slot: C[i][j] += sum_{g,s} A(g,s)[i] B(g,s)[j] with i (A) and j (B) the
+// lane's index within its group of 16.  The eight slots of a lane may hold
+// any pairs whose products belong to the same sum: eight values of k of one
+// term, or four values of k of two terms.  The complex product is taken as
+// four real products (no operand sums to split).
+typedef __bf16 bf4_t __attribute__((ext_vector_type(4)));
+typedef __bf16 bf8_t __attribute__((ext_vector_type(8)));
 
-// x = hi + lo with hi = bf16(x), lo = bf16(x - hi) (round to nearest even).
-__device__ __forceinline__ void split_bf16x4(const float* x, s4_t& hi, s4_t& lo) {
+struct Split4 {
+    bf4_t hi, lo;
+};
+
+__device__ __forceinline__ Split4 split4(const float (&x)[4]) {
+    Split4 s;
 #pragma unroll
     for (int q = 0; q < 4; ++q) {
         const __bf16 h = (__bf16)x[q];
-        const __bf16 l = (__bf16)(x[q] - (float)h);
-        hi[q] = (short)__builtin_bit_cast(unsigned short, h);
-        lo[q] = (short)__builtin_bit_cast(unsigned short, l);
+        s.hi[q] = h;
+        s.lo[q] = (__bf16)(x[q] - (float)h);
     }
+    return s;
 }
 
-__device__ __forceinline__ f4_t mfma_bf16(s4_t a, s4_t b, f4_t c) {
-    return __builtin_amdgcn_mfma_f32_16x16x16bf16_1k(a, b, c, 0, 0, 0);
+__device__ __forceinline__ bf8_t cat8(bf4_t a, bf4_t b) {
+    return __builtin_shufflevector(a, b, 0, 1, 2, 3, 4, 5, 6, 7);
 }
 
-// 3M complex product on BF16 hi/lo split operands with FP32 accumulation:
-// each real product a b is taken as a_hi b_hi + a_hi b_lo + a_lo b_hi (the
-// a_lo b_lo term is below FP32 rounding of the result's scale).  The 16x16x16
-// BF16 MFMA takes four consecutive k per lane group: A[i][16 kb + 4 g + q],
-// B[16 kb + 4 g + q][j].
-template <class G>
-__device__ __forceinline__ Tile<float> slot_mul_bf16s(const double* A, const double* B, const Lane& L) {
-    const float* Are = reinterpret_cast<const float*>(A);
-    const float* Aim = Are + G::PLANE;
-    const float* Bre = reinterpret_cast<const float*>(B);
-    const float* Bim = Bre + G::PLANE;
-    f4_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
-    const int arow = (16 * L.TI + L.j) * G::LD;
-    const int bcol = 16 * L.TJ + L.j;
-#pragma unroll
-    for (int kb = 0; kb < G::D / 16; ++kb) {
-        float ar[4], ai[4], as[4], br[4], bi[4], bs[4];
-#pragma unroll
-        for (int q = 0; q < 4; ++q) {
-            const int k = 16 * kb + 4 * L.g + q;
-            ar[q] = Are[arow + k];
-            ai[q] = Aim[arow + k];
-            br[q] = Bre[k * G::LD + bcol];
-            bi[q] = Bim[k * G::LD + bcol];
-            as[q] = ar[q] + ai[q];
-            bs[q] = br[q] + bi[q];
-        }
-        s4_t arh, arl, aih, ail, ash, asl, brh, brl, bih, bil, bsh, bsl;
-        split_bf16x4(ar, arh, arl);
-        split_bf16x4(ai, aih, ail);
-        split_bf16x4(as, ash, asl);
-        split_bf16x4(br, brh, brl);
-        split_bf16x4(bi, bih, bil);
-        split_bf16x4(bs, bsh, bsl);
-        t1 = mfma_bf16(arh, brh, t1);
-        t2 = mfma_bf16(aih, bih, t2);
-        t3 = mfma_bf16(ash, bsh, t3);
-        t1 = mfma_bf16(arh, brl, t1);
-        t2 = mfma_bf16(aih, bil, t2);
-        t3 = mfma_bf16(ash, bsl, t3);
-        t1 = mfma_bf16(arl, brh, t1);
-        t2 = mfma_bf16(ail, bih, t2);
-        t3 = mfma_bf16(asl, bsh, t3);
-    }
+__device__ __forceinline__ f4_t mfma_bf16x32(bf8_t a, bf8_t b, f4_t c) {
+    return __builtin_amdgcn_mfma_f32_16x16x32_bf16(a, b, c, 0, 0, 0);
+}
+
+// Register product of one-wave tiles (FP32 accumulator layout: a lane holds
+// k = 4g + r, r = 0..3, of its column), the A-slices given as
+// (a_r - i a_i)[r] as in reg_mul: Re = sum a_r Br + a_i Bi,
+// Im = sum a_r Bi - a_i Br.  Each x32 MFMA carries two four-k terms (the
+// tile's whole K = 16 twice), so a complex product takes six.
+__device__ __forceinline__ Tile<float> reg_mul_bf16x(const Split4& ar, const Split4& ai, const Split4& br,
+                                                     const Split4& bi) {
+    const bf4_t nah = -ai.hi, nal = -ai.lo;
+    f4_t re = {0, 0, 0, 0}, im = {0, 0, 0, 0};
+    re = mfma_bf16x32(cat8(ar.hi, ar.hi), cat8(br.hi, br.lo), re);
+    im = mfma_bf16x32(cat8(ar.hi, ar.hi), cat8(bi.hi, bi.lo), im);
+    re = mfma_bf16x32(cat8(ar.lo, ai.hi), cat8(br.hi, bi.hi), re);
+    im = mfma_bf16x32(cat8(ar.lo, nah), cat8(bi.hi, br.hi), im);
+    re = mfma_bf16x32(cat8(ai.hi, ai.lo), cat8(bi.lo, bi.hi), re);
+    im = mfma_bf16x32(cat8(nah, nal), cat8(br.lo, br.hi), im);
     Tile<float> out;
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
-        out.re[r] = t1[r] - t2[r];
-        out.im[r] = t3[r] - t1[r] - t2[r];
+        out.re[r] = re[r];
+        out.im[r] = im[r];
+    }
+    return out;
+}
+
+__device__ __forceinline__ Tile<float> reg_mul_bf16s(const float (&ar)[4], const float (&ai)[4],
+                                                     const Tile<float>& B) {
+    return reg_mul_bf16x(split4(ar), split4(ai), split4(B.re), split4(B.im));
+}
+
+// BF16 slots: a D x D complex matrix staged as four bf16 planes (hi and lo of
+// the real and of the imaginary part), row stride D + 8 (16-byte aligned
+// rows; sixteen lanes reading sixteen rows at one offset hit distinct
+// banks).  A slot holds either the rows of X (operand A, or a Hermitian B,
+// whose column j is the conjugate of its row j) or the rows of X^T (a
+// general operand B).  Each entry is split once, when it is staged.
+template <class G>
+struct BfSlot {
+    static constexpr int LDB = G::D + 8;
+    static constexpr int PL = G::D * LDB;   // bf16 per plane
+    static_assert(4 * PL * 2 <= G::SLOT * 8, "four bf16 planes fit a slot");
+};
+
+template <class G>
+__device__ __forceinline__ void slot_store_bf16(double* slot, const Tile<float>& t, const Lane& L, bool trans) {
+    using S = BfSlot<G>;
+    __bf16* pl = reinterpret_cast<__bf16*>(slot);
+    const Split4 sr = split4(t.re), si = split4(t.im);
+    const int col = 16 * L.TJ + L.j;
+    const int row0 = 16 * L.TI + 4 * L.g;   // rows row0 .. row0 + 3 (FP32 layout)
+    if (trans) {
+        // rows of X^T: the lane's four rows are four consecutive entries
+        const int at = col * S::LDB + row0;
+        *reinterpret_cast<bf4_t*>(pl + at) = sr.hi;
+        *reinterpret_cast<bf4_t*>(pl + S::PL + at) = sr.lo;
+        *reinterpret_cast<bf4_t*>(pl + 2 * S::PL + at) = si.hi;
+        *reinterpret_cast<bf4_t*>(pl + 3 * S::PL + at) = si.lo;
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const int at = (row0 + r) * S::LDB + col;
+            pl[at] = sr.hi[r];
+            pl[S::PL + at] = sr.lo[r];
+            pl[2 * S::PL + at] = si.hi[r];
+            pl[3 * S::PL + at] = si.lo[r];
+        }
+    }
+}
+
+// Tile (TI, TJ) of A B from BF16 slots: A holds the rows of A; B holds the
+// rows of B^T, or with bherm the rows of a Hermitian B (B[k][j] =
+// conj(B[j][k])).  Four real products, each three split terms, eight k per
+// lane and K = 32 per step; the four sums are combined with the signs of
+// the complex product at the end.
+template <class G>
+__device__ __forceinline__ Tile<float> slot_mul_bf16x(const double* A, const double* B, const Lane& L, bool bherm) {
+    using S = BfSlot<G>;
+    if constexpr (G::D == 16) {
+        // K = 16: four k per lane group (k = 4 g + q), two terms per
+        // instruction as in reg_mul_bf16x, whose A-slices a_r - i a_i take
+        // a_i = -Im A here; a Hermitian B's stored rows give Im B = -(stored)
+        const __bf16* pa = reinterpret_cast<const __bf16*>(A) + L.j * S::LDB + 4 * L.g;
+        const __bf16* pb = reinterpret_cast<const __bf16*>(B) + L.j * S::LDB + 4 * L.g;
+        Split4 ar, ai, br, bi;
+        ar.hi = *reinterpret_cast<const bf4_t*>(pa);
+        ar.lo = *reinterpret_cast<const bf4_t*>(pa + S::PL);
+        ai.hi = -*reinterpret_cast<const bf4_t*>(pa + 2 * S::PL);
+        ai.lo = -*reinterpret_cast<const bf4_t*>(pa + 3 * S::PL);
+        br.hi = *reinterpret_cast<const bf4_t*>(pb);
+        br.lo = *reinterpret_cast<const bf4_t*>(pb + S::PL);
+        bi.hi = *reinterpret_cast<const bf4_t*>(pb + 2 * S::PL);
+        bi.lo = *reinterpret_cast<const bf4_t*>(pb + 3 * S::PL);
+        if (bherm) {
+            bi.hi = -bi.hi;
+            bi.lo = -bi.lo;
+        }
+        return reg_mul_bf16x(ar, ai, br, bi);
+    }
+    const __bf16* pa = reinterpret_cast<const __bf16*>(A) + (16 * L.TI + L.j) * S::LDB + 8 * L.g;
+    const __bf16* pb = reinterpret_cast<const __bf16*>(B) + (16 * L.TJ + L.j) * S::LDB + 8 * L.g;
+    f4_t rr = {0, 0, 0, 0}, ii = {0, 0, 0, 0}, ri = {0, 0, 0, 0}, ir = {0, 0, 0, 0};
+#pragma unroll
+    for (int kb = 0; kb < G::D / 32; ++kb) {
+        const int o = 32 * kb;
+        const bf8_t arh = *reinterpret_cast<const bf8_t*>(pa + o);
+        const bf8_t arl = *reinterpret_cast<const bf8_t*>(pa + S::PL + o);
+        const bf8_t aih = *reinterpret_cast<const bf8_t*>(pa + 2 * S::PL + o);
+        const bf8_t ail = *reinterpret_cast<const bf8_t*>(pa + 3 * S::PL + o);
+        const bf8_t brh = *reinterpret_cast<const bf8_t*>(pb + o);
+        const bf8_t brl = *reinterpret_cast<const bf8_t*>(pb + S::PL + o);
+        const bf8_t bih = *reinterpret_cast<const bf8_t*>(pb + 2 * S::PL + o);
+        const bf8_t bil = *reinterpret_cast<const bf8_t*>(pb + 3 * S::PL + o);
+        rr = mfma_bf16x32(arh, brh, rr);
+        ii = mfma_bf16x32(aih, bih, ii);
+        ri = mfma_bf16x32(arh, bih, ri);
+        ir = mfma_bf16x32(aih, brh, ir);
+        rr = mfma_bf16x32(arh, brl, rr);
+        ii = mfma_bf16x32(aih, bil, ii);
+        ri = mfma_bf16x32(arh, bil, ri);
+        ir = mfma_bf16x32(aih, brl, ir);
+        rr = mfma_bf16x32(arl, brh, rr);
+        ii = mfma_bf16x32(ail, bih, ii);
+        ri = mfma_bf16x32(arl, bih, ri);
+        ir = mfma_bf16x32(ail, brh, ir);
+    }
+    // the stored imaginary part of B is Im B (rows of B^T) or -Im B (rows of
+    // a Hermitian B)
+    const float sg = bherm ? -1.0f : 1.0f;
+    Tile<float> out;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out.re[r] = rr[r] - sg * ii[r];
+        out.im[r] = sg * ri[r] + ir[r];
     }
     return out;
 }
@@ -369,46 +473,8 @@ __device__ __forceinline__ Tile<float> reg_mul4(const float (&ar)[4], const floa
     return out;
 }
 
-// The same product as 3M on BF16 hi/lo split operands (the BF16-split
-// mode): the 16x16x16 BF16 MFMA takes four consecutive k per lane group,
-// A[j][4 g + q] and B[4 g + q][j], which for one 16-wide tile are again the
-// lane's own four registers (rows 4 g + q of the FP32 accumulator layout).
-__device__ __forceinline__ Tile<float> reg_mul_bf16s(const float (&ar)[4], const float (&ai)[4],
-                                                     const Tile<float>& B) {
-    float as[4], bs[4];
-#pragma unroll
-    for (int q = 0; q < 4; ++q) {
-        as[q] = ar[q] - ai[q];
-        bs[q] = B.re[q] + B.im[q];
-    }
-    s4_t arh, arl, aih, ail, ash, asl, brh, brl, bih, bil, bsh, bsl;
-    split_bf16x4(ar, arh, arl);
-    split_bf16x4(ai, aih, ail);
-    split_bf16x4(as, ash, asl);
-    split_bf16x4(B.re, brh, brl);
-    split_bf16x4(B.im, bih, bil);
-    split_bf16x4(bs, bsh, bsl);
-    f4_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
-    t1 = mfma_bf16(arh, brh, t1);
-    t2 = mfma_bf16(aih, bih, t2);
-    t3 = mfma_bf16(ash, bsh, t3);
-    t1 = mfma_bf16(arh, brl, t1);
-    t2 = mfma_bf16(aih, bil, t2);
-    t3 = mfma_bf16(ash, bsl, t3);
-    t1 = mfma_bf16(arl, brh, t1);
-    t2 = mfma_bf16(ail, bih, t2);
-    t3 = mfma_bf16(asl, bsh, t3);
-    Tile<float> out;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        out.re[r] = t1[r] + t2[r];
-        out.im[r] = t3[r] - t1[r] + t2[r];
-    }
-    return out;
-}
-
 // Register product in the engine's product mode: FP64 and FP32-3M as 3M,
-// FP32 as four real products, BF16 split as split 3M.
+// FP32 as four real products, BF16 split as four split real products.
 template <typename T, int PMODE>
 __device__ __forceinline__ Tile<T> reg_mulP(const T (&ar)[4], const T (&ai)[4], const Tile<T>& B) {
     if constexpr (std::is_same<T, double>::value || PMODE == 1) return reg_mul<T>(ar, ai, B);
@@ -468,28 +534,58 @@ __device__ __forceinline__ void taylor_parts_reg(const Tile<T>& Gt, int m, const
     }
     const int qc = m / 2;        // highest power of Y in C
     const int qs = (m - 1) / 2;  // highest power of Y in S'
-    const Tile<T> Y = reg_mul_herm<T, PMODE>(Gt, Gt);
-    Tile<T> Sp = ident<T>(L);
-    axpy(C, cos_coef(1), Y);
-    if (qs >= 1) axpy(Sp, sin_coef(1), Y);
-    Tile<T> Yk = Y;
-    for (int k = 2; k <= qc; ++k) {
-        Yk = reg_mul_herm<T, PMODE>(Y, Yk);
-        axpy(C, cos_coef(k), Yk);
-        if (k <= qs) axpy(Sp, sin_coef(k), Yk);
+    if constexpr (!std::is_same<T, double>::value && PMODE == 2) {
+        // BF16 split: a Hermitian tile's split serves as the A-slices and as
+        // the B operand alike, so G and Y are split once for every product
+        // they enter
+        const Split4 gr = split4(Gt.re), gi = split4(Gt.im);
+        const Tile<T> Y = reg_mul_bf16x(gr, gi, gr, gi);
+        const Split4 yr = split4(Y.re), yi = split4(Y.im);
+        Tile<T> Sp = ident<T>(L);
+        axpy(C, cos_coef(1), Y);
+        if (qs >= 1) axpy(Sp, sin_coef(1), Y);
+        Tile<T> Yk = Y;
+        for (int k = 2; k <= qc; ++k) {
+            Yk = reg_mul_bf16x(yr, yi, split4(Yk.re), split4(Yk.im));
+            axpy(C, cos_coef(k), Yk);
+            if (k <= qs) axpy(Sp, sin_coef(k), Yk);
+        }
+        P = qs >= 1 ? reg_mul_bf16x(gr, gi, split4(Sp.re), split4(Sp.im)) : Gt;
+    } else {
+        const Tile<T> Y = reg_mul_herm<T, PMODE>(Gt, Gt);
+        Tile<T> Sp = ident<T>(L);
+        axpy(C, cos_coef(1), Y);
+        if (qs >= 1) axpy(Sp, sin_coef(1), Y);
+        Tile<T> Yk = Y;
+        for (int k = 2; k <= qc; ++k) {
+            Yk = reg_mul_herm<T, PMODE>(Y, Yk);
+            axpy(C, cos_coef(k), Yk);
+            if (k <= qs) axpy(Sp, sin_coef(k), Yk);
+        }
+        P = qs >= 1 ? reg_mul_herm<T, PMODE>(Gt, Sp) : Gt;
     }
-    P = qs >= 1 ? reg_mul_herm<T, PMODE>(Gt, Sp) : Gt;
 }
 
-// Product modes of the FP32 kernels: 0 four real products, 1 3M, 2 BF16-split 3M.
+// Product modes of the FP32 kernels: 0 four real products, 1 3M, 2 BF16
+// split (four split real products).  Staging and products of one mode go
+// together: stage() writes a slot in the mode's format (BF16 split: split
+// once into bf16 planes, the rows of X, or with trans of X^T), mulT()
+// multiplies two such slots (BF16 split: B staged as the rows of a
+// Hermitian matrix unless bherm is false, then as the rows of B^T).
 template <class G, typename T, int PMODE>
-__device__ __forceinline__ Tile<T> mulT(const double* A, const double* B, const Lane& L) {
+__device__ __forceinline__ void stage(double* slot, const Tile<T>& t, const Lane& L, bool trans = false) {
+    if constexpr (!std::is_same<T, double>::value && PMODE == 2) slot_store_bf16<G>(slot, t, L, trans);
+    else slot_store<G, T>(slot, t, L);
+}
+
+template <class G, typename T, int PMODE>
+__device__ __forceinline__ Tile<T> mulT(const double* A, const double* B, const Lane& L, bool bherm = true) {
     if constexpr (std::is_same<T, double>::value || PMODE == 0) {
         return slot_mul<G, T>(A, B, L);
     } else if constexpr (PMODE == 1) {
         return slot_mul_3m<G, float>(A, B, L);
     } else {
-        return slot_mul_bf16s<G>(A, B, L);
+        return slot_mul_bf16x<G>(A, B, L, bherm);
     }
 }
 
@@ -544,7 +640,7 @@ __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s
         const int qc = m / 2;        // highest power of Y in C
         const int qs = (m - 1) / 2;  // highest power of Y in S'
         team_sync<G>();
-        slot_store<G, T>(s0, Gt, L);
+        stage<G, T, PMODE>(s0, Gt, L);
         team_sync<G>();
         Tile<T> P = mulT<G, T, PMODE>(s0, s0, L);   // Y = G G
         Tile<T> Sp = ident<T>(L);
@@ -552,14 +648,14 @@ __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s
         if (qs >= 1) axpy(Sp, sin_coef(1), P);
         if (qc >= 2) {
             team_sync<G>();
-            slot_store<G, T>(s1, P, L);   // Y stays in s1
+            stage<G, T, PMODE>(s1, P, L);   // Y stays in s1
             team_sync<G>();
             for (int k = 2; k <= qc; ++k) {
                 if (k == 2) {
                     P = mulT<G, T, PMODE>(s1, s1, L);
                 } else {
                     team_sync<G>();
-                    slot_store<G, T>(s0, P, L);
+                    stage<G, T, PMODE>(s0, P, L);
                     team_sync<G>();
                     P = mulT<G, T, PMODE>(s0, s1, L);
                 }
@@ -569,8 +665,8 @@ __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s
         }
         if (qs >= 1) {
             team_sync<G>();
-            slot_store<G, T>(s0, Gt, L);
-            slot_store<G, T>(s1, Sp, L);
+            stage<G, T, PMODE>(s0, Gt, L);
+            stage<G, T, PMODE>(s1, Sp, L);
             team_sync<G>();
             S = mulT<G, T, PMODE>(s0, s1, L);
         } else {
@@ -689,10 +785,10 @@ __device__ __forceinline__ void chain_acc(Tile<double>& Q, const Tile<T>& E, con
         Qt.im[r] = (T)Q.im[r];
     }
     team_sync<G>();
-    slot_store<G, T>(s0, E, L);
-    slot_store<G, T>(s1, Qt, L);
+    stage<G, T, PMODE>(s0, E, L);
+    stage<G, T, PMODE>(s1, Qt, L, true);     // Q is no Hermitian matrix: B staged as Q^T
     team_sync<G>();
-    const Tile<T> P = mulT<G, T, PMODE>(s0, s1, L);
+    const Tile<T> P = mulT<G, T, PMODE>(s0, s1, L, false);
 #pragma unroll
     for (int r = 0; r < 4; ++r) {
         Q.re[r] += (double)P.re[r];

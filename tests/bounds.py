@@ -23,8 +23,10 @@ a d-term sum carries ~sqrt(d) u, n independent slice errors ~sqrt(n)):
 * BF16 split (hi*hi + hi*lo + lo*hi, FP32 accumulation): a split operand
   x_hi + x_lo carries 2^-16 relative error (two 8-bit significands) and the
   dropped lo*lo term is below it; per real product that is ~sqrt(d) 2^-16
-  relative in the model above, and a slice's four complex products are 3M
-  combinations whose imaginary parts double it (4 * 2 * 2 = 16):
+  relative in the model above; each part of a complex product is a sum of
+  two real products (four-product form), or in the 3M form carries up to
+  twice that, and a slice takes four complex products (4 * 2 * 2 = 16,
+  which covers either form):
       tol(n, d) = 16 sqrt(n) sqrt(d) 2^-16;
 * slices that need s squarings: each squaring doubles the relative error of
   the Taylor step, a factor 2^s.
