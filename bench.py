@@ -19,7 +19,8 @@ the launch stream), the oracle's CPU rate, and one object per leg:
   grad         fidelity-gradient evals/s on the 3-qubit register
   batch        512 uneven instances in one graph-captured launch
   cpu          the oracle's rate and every mode's error against it
-  fixed_error  smallest N reaching a target U(T) error, FP64 vs mixed
+  fixed_error  smallest N reaching a target U(T) error, FP64 vs mixed, on
+               the headline and the dim-64 systems (stored oracle references)
 ``--legs`` picks a subset (default: all); ``--legs copy`` adds a plain
 1 GiB device copy, the calibration kernel for the HBM byte counters.
 """
@@ -44,13 +45,13 @@ PEAK_HBM_GBS = 8000.0
 PEAK_BF16_TFLOPS = 2500.0
 PEAK = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "fp32_3m": PEAK_FP32_TFLOPS,
         "bf16_split": PEAK_BF16_TFLOPS}
-# HBM bytes per launch of the headline kernel from the FETCH_SIZE/WRITE_SIZE
-# passes (scaled by a 1 GiB copy: 2.0 x FETCH_SIZE KiB, 1.0 x WRITE_SIZE KiB),
-# valid only while the kernel's sources hash to the value they had then.
+# HBM bytes per launch of the headline kernel come from the FETCH_SIZE /
+# WRITE_SIZE passes summarised in this profile, whose pin block records the
+# per-dispatch counters, their copy-kernel scale factors and the sha256 of
+# the kernel's sources at the time; the traffic is reported only while the
+# sources still hash to that value.
 TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_kernel.h", "mfma_tiles.h", "mfma_tree.h", "engine_common.h", "pm_internal.h"]
-MEASURED_TRAFFIC = {"bytes": (2.0 * 4452.515625 + 1.0 * 2360.53125) * 1024.0,
-                    "sources_sha256": "71bb5a8361a990b82464b929e153d00db0a239e83f47f59f6225b56f6b6e040b",
-                    "profile": "profiles/propagate_d16_random_qudit_traffic.md"}
+TRAFFIC_PROFILE = "profiles/propagate_d16_random_qudit_traffic.md"
 LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "cf4", "trajectory", "grad", "grape", "batch", "cpu",
         "fixed_error"]
 
@@ -101,13 +102,56 @@ def algorithmic_flops(pm, w, precision, n_leaves: int) -> float:
     return 8.0 * D ** 3 * prods + 4.0 * M * D * D * n
 
 
-def headline_traffic():
+def issued_mfma_flops(pm, w, precision, n_leaves: int) -> float:
+    """MFMA flops the kernel issues for one propagation of w on the 16/32/64
+    engines: FP64 and 3M products are three real D x D x D products (6 D^3
+    flops per complex product), FP32 4M products four (8 D^3), BF16-split
+    products four real products of three BF16 terms each (24 D^3); the
+    expand and the plan run on the vector ALU and are not counted."""
+    per = {0: 6.0, 1: 8.0, 2: 6.0, 3: 24.0}[precision]
+    alg = algorithmic_flops(pm, w, precision, n_leaves)
+    D = engine_dim(w.dim)
+    B, _ = pm.build_basis_host(w.H0, w.Hk, w.order)
+    expand = 4.0 * B.shape[0] * D * D * w.n_slices
+    return (alg - expand) / 8.0 * per
+
+
+def traffic_pin(path: str = TRAFFIC_PROFILE) -> dict:
+    """key: value lines of the profile's pin block (<!-- pin ... -->)."""
+    pin = {}
+    try:
+        with open(os.path.join(ROOT, path)) as f:
+            txt = f.read()
+    except OSError:
+        return pin
+    if "<!-- pin" not in txt:
+        return pin
+    block = txt.split("<!-- pin", 1)[1].split("-->", 1)[0]
+    for line in block.splitlines():
+        if ":" in line:
+            k, v = line.split(":", 1)
+            pin[k.strip()] = v.strip()
+    return pin
+
+
+def sources_sha256() -> str:
     import hashlib
     h = hashlib.sha256()
     for f in TRAFFIC_SOURCES:
         with open(os.path.join(ROOT, "paper_2108_07126_amd", "csrc", f), "rb") as fh:
             h.update(fh.read())
-    return MEASURED_TRAFFIC["bytes"] if h.hexdigest() == MEASURED_TRAFFIC["sources_sha256"] else None
+    return h.hexdigest()
+
+
+def headline_traffic():
+    pin = traffic_pin()
+    try:
+        if pin.get("sources_sha256") != sources_sha256():
+            return None
+        return 1024.0 * (float(pin["fetch_scale"]) * float(pin["fetch_kib_per_dispatch"]) +
+                         float(pin["write_scale"]) * float(pin["write_kib_per_dispatch"]))
+    except (KeyError, ValueError):
+        return None
 
 
 def time_launches(fn, steps: int, warmup: int):
@@ -128,6 +172,17 @@ def time_launches(fn, steps: int, warmup: int):
     wall = (time.perf_counter() - t0) * 1e3 / steps
     per = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     return wall, per
+
+
+def host_cpu_model() -> str:
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    return line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return "unknown"
 
 
 def blas_threads() -> int:
@@ -166,9 +221,12 @@ def leg_d64(pm, torch, dev, args, out):
         wall, k = time_launches(lambda: ctx.equiprop_dev(s_dev, w.h, U), max(3, args.steps // 4), 2)
         fl = flops_of(pm, ctx, w, prec)
         ach = fl / (k * 1e-3) / 1e12
+        iss = issued_mfma_flops(pm, w, prec, ctx.launch_shape(w.n_samples)[1])
         res[name] = {"steps_per_s": w.n_slices / (wall * 1e-3), "ms_per_step": wall, "kernel_ms": k,
                      "algorithmic_flop_per_launch": fl, "achieved_tflops": ach, "peak_tflops": PEAK[name],
-                     "frac": ach / PEAK[name], "launch_shape": list(ctx.launch_shape(w.n_samples))}
+                     "frac": ach / PEAK[name], "issued_mfma_flop_per_launch": iss,
+                     "issued_mfma_frac": iss / (k * 1e-3) / 1e12 / PEAK[name],
+                     "launch_shape": list(ctx.launch_shape(w.n_samples))}
         Ug[name] = U.cpu().numpy()
         ctx.close()
     out["d64"] = res
@@ -262,7 +320,8 @@ def leg_small(pm, torch, dev, args, out):
             row[name] = {"steps_per_s": N / (wall * 1e-3), "kernel_ms": k, "kernel_ms_without_slices": k_nos,
                          "algorithmic_bytes": nbytes, "achieved_gbs": gbs, "frac_hbm": gbs / PEAK_HBM_GBS,
                          "algorithmic_flops": flops, "flop_per_byte": flops / nbytes,
-                         "bound": "hbm" if nbytes / (PEAK_HBM_GBS * 1e9) >= flops / (peak * 1e12) else "mfma",
+                         "bound": ("hbm" if nbytes / (PEAK_HBM_GBS * 1e9) >= flops / (peak * 1e12)
+                                   else ("alu" if d <= 4 else "mfma")),
                          "roofline_ms": t_roof, "frac_roofline": t_roof / k}
             del sl
             ctx.close()
@@ -378,6 +437,88 @@ def leg_grad_independent(pm, torch, dev, synth, n: int = 64):
     return {"evaluations": n, "streams": GRAD_STREAMS, "ms_per_round": t * 1e3, "evals_per_s": n / t}
 
 
+GOLDEN = os.path.join(ROOT, "tests", "golden", "full_size_oracle.npz")
+
+
+def rel_frobenius(a, b) -> float:
+    return float(np.linalg.norm(a - b) / np.linalg.norm(b))
+
+
+def leg_fixed_error(pm, torch, dev, modes):
+    """Steps/s at a fixed U(T) error, FP64 against the reduced precisions.
+
+    For each workload the span T stays fixed and N = 2^n slices of width
+    T / N are propagated in every mode; the error of U(T) is taken against
+    the oracle's U(T) over the same span, stored by
+    tests/golden/make_full_size.py: at the random qudit's own N (2^17,
+    order 4), and for the dim-64 sweep at eight times its N (2^19, midpoint
+    rule; its own 2^16 slices carry a discretisation error of about 2e-3,
+    so its targets are 1e-2 and 1e-3 instead of the qudit's 1e-4 and 1e-6).
+    N is searched only up to a quarter of the reference's N, where the
+    reference's own discretisation error is below 1/4^p of the measured one
+    (p the order), so the measured errors are the coarse runs' own.  For each
+    target the smallest N meeting it is reported with its kernel time (HIP
+    events on the launch stream) and wall time, and the FP64 / mode
+    kernel-time ratio at the target: the speed-up of the mode at equal
+    accuracy."""
+    import synth
+    if not os.path.exists(GOLDEN):
+        return {"skipped": "no stored oracle reference"}
+    with np.load(GOLDEN) as z:
+        refs = {k: z[k] for k in ("random_qudit", "precision_sweep_fine") if k in z.files}
+    # (label, reference key, workload at N slices of width h, reference N, span, order, targets, search)
+    cases = [("random_qudit_d16_K3_magnus4", "random_qudit",
+              lambda n, h: synth.random_qudit(n_slices=n, h=h), 2 ** 17, 2 ** 17 * 1e-3, 4, (1e-4, 1e-6),
+              range(9, 16)),
+             ("precision_sweep_d64_K2_midpoint", "precision_sweep_fine",
+              lambda n, h: synth.precision_sweep(n_slices=n, h=h), 2 ** 19, 2 ** 16 * 1e-2, 2, (1e-2, 1e-3),
+              range(12, 18))]
+    res = {}
+    for label, key, make, n_ref, T, slope, targets, search in cases:
+        if key not in refs:
+            res[label] = {"skipped": "no stored oracle reference"}
+            continue
+        row = {"reference": f"oracle U(T) at N = {n_ref} (order {slope}), searched N <= {n_ref // 4}: the "
+                            f"reference's own discretisation error is at most 1/{4 ** slope} of the "
+                            f"measured error there", "span_T": T, "targets": list(targets)}
+        curves = {}
+        for name, prec in modes:
+            ctx = pm.Context(0, prec)
+            w0 = make(2 ** search.start, T / 2 ** search.start)
+            ctx.set_hamiltonian(w0.H0, w0.Hk, w0.order)
+            cur = {}
+            for n in search:
+                nn = 2 ** n
+                wn = make(nn, T / nn)
+                sd = torch.from_numpy(wn.samples).to(dev)
+                Ud = torch.zeros((wn.dim, wn.dim), dtype=torch.complex128, device=dev)
+                wall, kms = time_launches(lambda: ctx.equiprop_dev(sd, wn.h, Ud), 5, 2)
+                cur[nn] = {"err": rel_frobenius(Ud.cpu().numpy(), refs[key]), "ms": wall, "kernel_ms": kms}
+            ctx.close()
+            curves[name] = cur
+            row[name] = {str(k): v for k, v in cur.items()}
+        summ = {}
+        for eps in targets:
+            base = None
+            for name, _ in modes:
+                ok = [k for k, v in curves[name].items() if v["err"] <= eps]
+                if not ok:
+                    summ[f"{name}_eps_{eps:.0e}"] = None
+                    continue
+                k = min(ok)
+                v = curves[name][k]
+                e = {"n_slices": k, "kernel_ms": v["kernel_ms"], "ms": v["ms"],
+                     "steps_per_s": k / (v["kernel_ms"] * 1e-3)}
+                if name == "fp64":
+                    base = v["kernel_ms"]
+                elif base is not None:
+                    e["fp64_over_mode_kernel_time"] = base / v["kernel_ms"]
+                summ[f"{name}_eps_{eps:.0e}"] = e
+        row["summary"] = summ
+        res[label] = row
+    return res
+
+
 def leg_copy(torch, dev, out):
     """A plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB): the
     calibration kernel for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -410,7 +551,7 @@ def main():
         print(f"unknown legs: {sorted(unknown)}", file=sys.stderr)
         sys.exit(2)
     if args.skip_cpu:
-        legs -= {"cpu", "fixed_error"}
+        legs.discard("cpu")
     if args.skip_fixed_error:
         legs.discard("fixed_error")
     if args.skip_batch:
@@ -441,6 +582,7 @@ def main():
     wall64, k64 = timing["fp64"]
     chunk, chains, leaves = ctxs["fp64"].launch_shape(w.n_samples)
     ach64 = flops["fp64"] / (k64 * 1e-3) / 1e12
+    issued64 = issued_mfma_flops(pm, w, pm.PM_FP64, chains)
 
     out = {
         "metric": METRIC,
@@ -460,10 +602,13 @@ def main():
                    "leaves": leaves},
         "roofline": {"bound": "mfma", "achieved": ach64, "peak": PEAK_FP64_TFLOPS, "unit": "TFLOP/s",
                      "frac": ach64 / PEAK_FP64_TFLOPS, "traffic": headline_traffic(),
-                     "traffic_unit": "bytes per launch",
+                     "traffic_unit": "bytes per launch", "traffic_profile": TRAFFIC_PROFILE,
                      "algorithmic_bytes_per_launch": w.samples.size * 8 + d * d * 16,
-                     "kernel": "propagate_mfma<double,16,4,true,0,false,false>", "kernel_ms": k64,
-                     "algorithmic_flop_per_launch": flops["fp64"]},
+                     "kernel": "propagate_mfma<double,16,4,true,0,false,false,false>", "kernel_ms": k64,
+                     "algorithmic_flop_per_launch": flops["fp64"],
+                     "frac_basis": "algorithmic flops: 8 d^3 per complex product",
+                     "issued_mfma_flop_per_launch": issued64,
+                     "issued_mfma_frac": issued64 / (k64 * 1e-3) / 1e12 / PEAK_FP64_TFLOPS},
     }
     if "precisions" in legs:
         out["precisions"] = {name: {"steps_per_s": N / (timing[name][0] * 1e-3), "ms_per_step": timing[name][0],
@@ -561,7 +706,8 @@ def main():
         Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, w.order)
         dt_cpu = time.perf_counter() - t0
         out["cpu_baseline"] = {"value": N / dt_cpu, "unit": "steps/s", "cores": blas_threads(), "kind": "oracle",
-                               "sample": f"the whole workload ({N} slices, one run, {dt_cpu:.1f} s)"}
+                               "sample": f"the whole workload ({N} slices, one run, {dt_cpu:.1f} s)",
+                               "host_nproc": os.cpu_count(), "host_cpu": host_cpu_model()}
         out["error_vs_oracle"] = {name: orc.relative_frobenius(Ug[name], Uo) for name, _ in modes}
         if "chebyshev" in out:
             row = out["chebyshev"]["random_qudit_d16_N2^17"]
@@ -584,29 +730,8 @@ def main():
                     e64[name] = orc.relative_frobenius(ctx.equiprop(wp.samples, wp.h), Uo64)
             out["d64"]["error_vs_oracle_first_4096_slices"] = e64
 
-    if "fixed_error" in legs and Uo is not None:
-        import oracle.propagator as orc
-        # same T, coarser slicing: smallest N=2^n meeting each target error
-        T = N * w.h
-        res = {"reference": "oracle at the workload's own N (2^17 slices)"}
-        summ = {}
-        for name, _ in modes:
-            errs = {}
-            for n in range(8, 18):
-                nn = 2 ** n
-                wn = synth.random_qudit(n_slices=nn, h=T / nn)
-                sd = torch.from_numpy(wn.samples).to(dev)
-                Ud = torch.zeros((d, d), dtype=torch.complex128, device=dev)
-                wall, _ = time_launches(lambda: ctxs[name].equiprop_dev(sd, wn.h, Ud), 5, 2)
-                errs[nn] = (orc.relative_frobenius(Ud.cpu().numpy(), Uo), wall)
-            res[name] = {str(k): {"err": v[0], "ms": v[1]} for k, v in errs.items()}
-            for eps in (1e-4, 1e-6):
-                ok = [k for k, v in errs.items() if v[0] <= eps]
-                summ[f"{name}_eps_{eps:.0e}"] = ({"n_slices": min(ok), "ms": errs[min(ok)][1],
-                                                  "steps_per_s": min(ok) / (errs[min(ok)][1] * 1e-3)}
-                                                 if ok else None)
-        res["summary"] = summ
-        out["fixed_error"] = res
+    if "fixed_error" in legs:
+        out["fixed_error"] = leg_fixed_error(pm, torch, dev, modes)
 
     if "chebyshev" in out:
         for row in out["chebyshev"].values():

@@ -10,6 +10,9 @@ nothing comes from the library.
 Contents:
   random_qudit      U(T) of the d = 16 random qudit at N = 2^17 (order 4)
   precision_sweep   U(T) of the d = 64 precision sweep at N = 2^16 (order 2)
+  precision_sweep_fine
+                    U(T) of the same system over the same span at N = 2^19
+                    (the reference of the fixed-error comparison at d = 64)
   batch_index       instance indices of the 512-instance batch that are kept:
                     every instance of dimension <= 16, the two longest of
                     dimension 32 and of dimension 64 with order 2, and the
@@ -18,7 +21,13 @@ Contents:
                     entries), one more entry for the end
   batch_U           the kept instances' U(T), concatenated row-major
 
-Run:  python tests/golden/make_full_size.py   (about 3 minutes on 8 cores)
+Run:  python tests/golden/make_full_size.py   (about 6 minutes on 8 cores)
+
+The fine reference takes the oracle's steps in the oracle's order -- the
+slice propagators of each 8192-slice block by eigendecomposition
+(``slice_propagators``, computed for several blocks at once in worker
+processes), multiplied in sequence into U (``ordered_product``), exactly
+the blocks and products of ``propagate``.
 """
 from __future__ import annotations
 
@@ -71,6 +80,30 @@ def _job(key):
     return key, U, time.time() - t0
 
 
+FINE_N = 2 ** 19
+BLOCK = 8192
+
+
+def _fine_block(rng):
+    s, e = rng
+    w = synth.precision_sweep(n_slices=FINE_N, h=2 ** 16 * 0.01 / FINE_N)
+    return orc.slice_propagators(w.H0, w.Hk, w.samples, w.h, w.order, s, e)
+
+
+def fine_reference(ex) -> np.ndarray:
+    """U(T) of the d = 64 sweep at 2^18 slices: blocks of slice propagators
+    from the pool (at most eight in flight), multiplied in order."""
+    U = np.eye(64, dtype=np.complex128)
+    starts = list(range(0, FINE_N, BLOCK))
+    futs, nxt = {}, 0
+    for i in range(len(starts)):
+        while nxt < len(starts) and nxt < i + 8:
+            futs[nxt] = ex.submit(_fine_block, (starts[nxt], min(FINE_N, starts[nxt] + BLOCK)))
+            nxt += 1
+        U = orc.ordered_product(futs.pop(i).result(), U)
+    return U
+
+
 def main() -> None:
     insts = synth.batched_instances(512)
     sel = batch_selection(insts)
@@ -85,12 +118,16 @@ def main() -> None:
             res[key] = U
             if dt > 5:
                 print(f"{key}: {dt:.1f} s", flush=True)
+        t0 = time.time()
+        res["precision_sweep_fine"] = fine_reference(ex)
+        print(f"precision_sweep_fine: {time.time() - t0:.1f} s", flush=True)
     offs = [0]
     flat = []
     for i in sel:
         flat.append(res[str(i)].reshape(-1))
         offs.append(offs[-1] + flat[-1].size)
     np.savez_compressed(OUT, random_qudit=res["random_qudit"], precision_sweep=res["precision_sweep"],
+                        precision_sweep_fine=res["precision_sweep_fine"],
                         batch_index=np.array(sel, np.int64), batch_offset=np.array(offs, np.int64),
                         batch_U=np.concatenate(flat))
     print(f"wrote {OUT}: {len(sel)} batch instances", flush=True)
