@@ -225,15 +225,21 @@ propagate_mfma(PropParams p) {
                 // without squarings, the chain product straight from it, all
                 // in registers
                 Tile<double> C, P;
-                taylor_parts_reg<double>(Gt, m, L, C, P);
+                // slice pairs: the stacked block products (half the MFMA work)
+                taylor_parts_reg<double, 0, false, PAIR>(Gt, m, L, C, P);
                 if (s == 0) {
                     if (p.slices_out) store_out(t, combine_cp<double>(C, P));
-                    Q = reg_mul_cp<double>(C, P, Q);
+                    Q = reg_mul_cp<double, 0, PAIR>(C, P, Q);
                     continue;
                 }
                 U = combine_cp<double>(C, P);
             } else {
                 U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);
+            }
+            if constexpr (PAIR) {
+                // full 16-wide products follow: clear the cross blocks
+                pair_mask(U, L);
+                pair_mask(Q, L);
             }
             if (s > 0) U = square_n<G, double>(U, s, L, s0);
             if (p.slices_out) store_out(t, U);
@@ -292,6 +298,11 @@ propagate_mfma(PropParams p) {
                 const double* later = slots + (team + st) * 2 * G::SLOT + G::SLOT;
                 Qd = slot_mul<G, double>(later, s1, L);
             }
+        }
+        if constexpr (G::TW == 1 && 2 * NT == kFanIn) {
+            // the block's teams stay together into the tree
+            tree_reduce_teams<G, NT>(p, blockIdx.x, Qd, L, team, slots, tick);
+            return;
         }
         if (team != 0) return;
     }

@@ -473,25 +473,66 @@ __device__ __forceinline__ Tile<float> reg_mul4(const float (&ar)[4], const floa
     return out;
 }
 
+// Slice pairs (FP64): one-wave tiles whose two 8 x 8 diagonal blocks hold
+// two independent slices are multiplied as the stacked product
+// [A_a; A_b] [B_a, B_b] -- K = 8 instead of 16, two k-slices instead of
+// four, half the MFMA work of the embedded product.  For k-slice s the lane
+// (g, j) supplies its register s (its column in the first block: row
+// g + 4s) or s + 2 (second block: row 8 + g + 4s), for the A-slices as for
+// the B operand.  The result's diagonal blocks are A_a B_a and A_b B_b in
+// place; its off-diagonal blocks hold cross products of the two slices,
+// which no later product reads (pair_mask clears them where a full product
+// follows).
+__device__ __forceinline__ Tile<double> reg_mul_stk(const double (&ar)[4], const double (&ai)[4],
+                                                    const Tile<double>& B) {
+    const bool hi = (__lane_id() & 8) != 0;
+    d4_t t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
+#pragma unroll
+    for (int q = 0; q < 2; ++q) {
+        const double a_r = hi ? ar[q + 2] : ar[q], a_i = hi ? ai[q + 2] : ai[q];
+        const double b_r = hi ? B.re[q + 2] : B.re[q], b_i = hi ? B.im[q + 2] : B.im[q];
+        t1 = mfma16(a_r, b_r, t1);
+        t2 = mfma16(a_i, b_i, t2);
+        t3 = mfma16(a_r - a_i, b_r + b_i, t3);
+    }
+    Tile<double> out;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        out.re[r] = t1[r] + t2[r];
+        out.im[r] = t3[r] - t1[r] + t2[r];
+    }
+    return out;
+}
+
+// Zero the off-diagonal 8 x 8 blocks of a slice-pair tile (FP64 layout:
+// register r holds row g + 4r, in the second block for r >= 2).
+__device__ __forceinline__ void pair_mask(Tile<double>& t, const Lane& L) {
+#pragma unroll
+    for (int r = 0; r < 4; ++r)
+        if ((r >= 2) != (L.j >= 8)) t.re[r] = t.im[r] = 0.0;
+}
+
 // Register product in the engine's product mode: FP64 and FP32-3M as 3M,
-// FP32 as four real products, BF16 split as four split real products.
-template <typename T, int PMODE>
+// FP32 as four real products, BF16 split as four split real products; STK:
+// the stacked slice-pair product (FP64).
+template <typename T, int PMODE, bool STK = false>
 __device__ __forceinline__ Tile<T> reg_mulP(const T (&ar)[4], const T (&ai)[4], const Tile<T>& B) {
-    if constexpr (std::is_same<T, double>::value || PMODE == 1) return reg_mul<T>(ar, ai, B);
+    if constexpr (STK) return reg_mul_stk(ar, ai, B);
+    else if constexpr (std::is_same<T, double>::value || PMODE == 1) return reg_mul<T>(ar, ai, B);
     else if constexpr (PMODE == 0) return reg_mul4(ar, ai, B);
     else return reg_mul_bf16s(ar, ai, B);
 }
 
 // A B for a Hermitian A (the A-slices are conj of the lane's own registers).
-template <typename T, int PMODE = 0>
+template <typename T, int PMODE = 0, bool STK = false>
 __device__ __forceinline__ Tile<T> reg_mul_herm(const Tile<T>& A, const Tile<T>& B) {
-    return reg_mulP<T, PMODE>(A.re, A.im, B);
+    return reg_mulP<T, PMODE, STK>(A.re, A.im, B);
 }
 
 // (C - i P) B for Hermitian C and P: the A-slice of C - i P at (j, k) is
 // conj(C[k][j]) - i conj(P[k][j]) = (C_re - P_im) - i (C_im + P_re) of the
 // lane's own registers.
-template <typename T, int PMODE = 0>
+template <typename T, int PMODE = 0, bool STK = false>
 __device__ __forceinline__ Tile<T> reg_mul_cp(const Tile<T>& C, const Tile<T>& P, const Tile<T>& B) {
     T ar[4], ai[4];
 #pragma unroll
@@ -499,7 +540,7 @@ __device__ __forceinline__ Tile<T> reg_mul_cp(const Tile<T>& C, const Tile<T>& P
         ar[r] = C.re[r] - P.im[r];
         ai[r] = C.im[r] + P.re[r];
     }
-    return reg_mulP<T, PMODE>(ar, ai, B);
+    return reg_mulP<T, PMODE, STK>(ar, ai, B);
 }
 
 // C - i P as one tile.
@@ -520,7 +561,7 @@ __device__ __forceinline__ Tile<T> combine_cp(const Tile<T>& C, const Tile<T>& P
 // every product has a Hermitian left factor, so all of them stay in
 // registers.  With EXCESS the identity term of C is left out (C - i P is
 // then exp(-i G) - I, accurate relative to ||G||).
-template <typename T, int PMODE = 0, bool EXCESS = false>
+template <typename T, int PMODE = 0, bool EXCESS = false, bool STK = false>
 __device__ __forceinline__ void taylor_parts_reg(const Tile<T>& Gt, int m, const Lane& L, Tile<T>& C, Tile<T>& P) {
     if constexpr (EXCESS) {
 #pragma unroll
@@ -552,17 +593,17 @@ __device__ __forceinline__ void taylor_parts_reg(const Tile<T>& Gt, int m, const
         }
         P = qs >= 1 ? reg_mul_bf16x(gr, gi, split4(Sp.re), split4(Sp.im)) : Gt;
     } else {
-        const Tile<T> Y = reg_mul_herm<T, PMODE>(Gt, Gt);
+        const Tile<T> Y = reg_mul_herm<T, PMODE, STK>(Gt, Gt);
         Tile<T> Sp = ident<T>(L);
         axpy(C, cos_coef(1), Y);
         if (qs >= 1) axpy(Sp, sin_coef(1), Y);
         Tile<T> Yk = Y;
         for (int k = 2; k <= qc; ++k) {
-            Yk = reg_mul_herm<T, PMODE>(Y, Yk);
+            Yk = reg_mul_herm<T, PMODE, STK>(Y, Yk);
             axpy(C, cos_coef(k), Yk);
             if (k <= qs) axpy(Sp, sin_coef(k), Yk);
         }
-        P = qs >= 1 ? reg_mul_herm<T, PMODE>(Gt, Sp) : Gt;
+        P = qs >= 1 ? reg_mul_herm<T, PMODE, STK>(Gt, Sp) : Gt;
     }
 }
 

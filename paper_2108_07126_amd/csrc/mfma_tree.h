@@ -127,6 +127,90 @@ __device__ void tree_reduce_groups(const PropParams& p, int64_t leaf, Tile<doubl
     store_root<G>(p, Q, L);
 }
 
+// The same tree for a block of NT one-wave teams (16-wide tiles) that all
+// stay into it: team 0 publishes the block's node and takes the group's
+// ticket, and the outcome goes to every team through LDS.  When the block is
+// its group's last arrival, team 0 loads the group's nodes together and
+// stages node q in LDS slot q; the group's product is then formed pairwise,
+// slot q + w times slot q into slot q for w = 1, 2, 4 (later nodes on the
+// left), four products at once in the first round: three dependent products
+// per level instead of seven.  Same nodes and root as tree_reduce_groups up
+// to the association inside each group.
+template <class G, int NT>
+__device__ void tree_reduce_teams(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L, int team,
+                                  double* slots, int* tick) {
+    static_assert(G::TW == 1 && 2 * NT == kFanIn, "one slot per group member");
+    constexpr int64_t NN = (int64_t)G::D * G::D * 2;
+    int64_t idx = leaf, cnt = p.n_leaves, off = 0;
+    while (cnt > 1) {
+        const int64_t pcnt = (cnt + kFanIn - 1) / kFanIn, poff = off + cnt, grp = idx / kFanIn;
+        const int64_t first = grp * kFanIn;
+        const int members = (int)(min(cnt, first + kFanIn) - first);
+        if (members == 1) {
+            if (p.store_nodes && team == 0) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
+        } else {
+            if (team == 0) {
+                node_store<G>(p.nodes + (off + idx) * NN, Q, L);
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                unsigned v = 0;
+                if (L.lane == 0) v = atomicAdd(&p.counters[poff + grp], 1u);
+                const unsigned t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(v, 0));
+                if (t == (unsigned)(members - 1)) {
+                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
+                    if (L.lane == 0) atomicExch(&p.counters[poff + grp], 0u);
+                }
+                if (L.lane == 0) *tick = (int)t;
+            }
+            __syncthreads();
+            const int t = *tick;
+            __syncthreads();
+            if (t != members - 1) return;   // the whole block leaves
+            if (team == 0) {
+                // four nodes in flight at a time (the registers of eight
+                // would spill at three waves per SIMD)
+#pragma unroll
+                for (int h = 0; h < kFanIn; h += kFanIn / 2) {
+                    Tile<double> X[kFanIn / 2];
+#pragma unroll
+                    for (int q = 0; q < kFanIn / 2; ++q)
+                        X[q] = (h + q < members && first + h + q != idx)
+                                   ? node_load<G>(p.nodes + (off + first + h + q) * NN, L)
+                                   : Q;
+#pragma unroll
+                    for (int q = 0; q < kFanIn / 2; ++q)
+                        if (h + q < members) slot_store<G, double>(slots + (h + q) * G::SLOT, X[q], L);
+                }
+            }
+            __syncthreads();
+#pragma unroll
+            for (int w = 1; w < kFanIn; w <<= 1) {
+                const int q = 2 * w * team;
+                const bool act = q + w < members;
+                Tile<double> P;
+                if (act) P = slot_mul<G, double>(slots + (q + w) * G::SLOT, slots + q * G::SLOT, L);
+                __syncthreads();
+                if (act) slot_store<G, double>(slots + q * G::SLOT, P, L);
+                __syncthreads();
+            }
+            if (team == 0) {
+                const int col = L.j;
+#pragma unroll
+                for (int r = 0; r < 4; ++r) {
+                    const int row = crow<double>(L.g, r);
+                    Q.re[r] = slots[row * G::LD + col];
+                    Q.im[r] = slots[G::PLANE + row * G::LD + col];
+                }
+            }
+        }
+        idx = grp;
+        off = poff;
+        cnt = pcnt;
+    }
+    if (team != 0) return;
+    if (p.store_nodes) node_store<G>(p.nodes + off * NN, Q, L);
+    store_root<G>(p, Q, L);
+}
+
 // The product tree over the chain (or block) products.
 template <class G>
 __device__ void tree_reduce(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L,
