@@ -218,20 +218,27 @@ propagate_mfma(PropParams p) {
         if constexpr (kF64) {
             // exponentiate, square, store, chain product Q <- U Q
             Tile<T> U;
-            if constexpr (CH) {
-                U = cheb_exp<G>(Gt, m, p.ctheta[m], p.cheb_j + m * (kMaxCheb + 1), L, s0, s1);
-            } else if constexpr (G::TW == 1) {
+            if constexpr (G::TW == 1) {
                 // one-wave team: the series as the Hermitian pair C - i P and,
                 // without squarings, the chain product straight from it, all
                 // in registers
                 Tile<double> C, P;
-                // slice pairs: the stacked block products (half the MFMA work)
-                taylor_parts_reg<double, 0, false, PAIR>(Gt, m, L, C, P);
+                if constexpr (CH)
+                    cheb_parts<G>(Gt, m, p.ctheta[m], p.cheb_j + kChebSplitOffset + m * 2 * kChebHalf, L, s0,
+                                  s1, C, P);
+                else
+                    // slice pairs: the stacked block products (half the MFMA work)
+                    taylor_parts_reg<double, 0, false, PAIR>(Gt, m, L, C, P);
                 if (s == 0) {
                     if (p.slices_out) store_out(t, combine_cp<double>(C, P));
                     Q = reg_mul_cp<double, 0, PAIR>(C, P, Q);
                     continue;
                 }
+                U = combine_cp<double>(C, P);
+            } else if constexpr (CH) {
+                Tile<double> C, P;
+                cheb_parts<G>(Gt, m, p.ctheta[m], p.cheb_j + kChebSplitOffset + m * 2 * kChebHalf, L, s0, s1, C,
+                              P);
                 U = combine_cp<double>(C, P);
             } else {
                 U = taylor_exp<G, T, PMODE>(Gt, m, L, s0, s1);

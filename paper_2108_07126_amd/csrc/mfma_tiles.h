@@ -723,68 +723,6 @@ __device__ Tile<T> taylor_exp(const Tile<T>& Gt, int m, const Lane& L, double* s
     return U;
 }
 
-// exp(-i G) for a (pre-scaled) Hermitian tile set by the degree-m Chebyshev
-// series on the interval [-theta, theta] that holds its spectrum
-// (eq. chebychev_series with alpha = -theta, beta = theta, so the phase
-// factor is 1): X = G / theta, a_k = (-i)^k J_k(theta) (row `jk` of the
-// coefficient table), and the Clenshaw recurrence of Algorithm 1,
-// D_k = a_k I + 2 X D_{k+1} - D_{k+2}, result D_0 - D_2.  m products.  FP64.
-template <class G>
-__device__ Tile<double> cheb_exp(const Tile<double>& Gt, int m, double theta, const double* jk, const Lane& L,
-                                 double* s0, double* s1) {
-    const double inv = 1.0 / theta;
-    Tile<double> X, D1, D2, keep;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        X.re[r] = Gt.re[r] * inv;
-        X.im[r] = Gt.im[r] * inv;
-        D1.re[r] = D1.im[r] = D2.re[r] = D2.im[r] = keep.re[r] = keep.im[r] = 0.0;
-    }
-    if constexpr (G::TW != 1) {
-        team_sync<G>();
-        slot_store<G, double>(s0, X, L);   // X stays in s0
-    }
-    for (int k = m; k >= 0; --k) {
-        Tile<double> P;
-        if (k < m) {
-            if constexpr (G::TW == 1) {
-                // one-wave team: X is Hermitian, so X D1 comes from registers
-                P = reg_mul_herm<double>(X, D1);
-            } else {
-                team_sync<G>();
-                slot_store<G, double>(s1, D1, L);
-                team_sync<G>();
-                P = slot_mul<G, double>(s0, s1, L);
-            }
-        } else {
-#pragma unroll
-            for (int r = 0; r < 4; ++r) P.re[r] = P.im[r] = 0.0;
-        }
-        // a_k = (-i)^k J_k: real for even k (sign + - + -), imaginary for odd
-        const double jv = jk[k];
-        const int q = k & 3;
-        const double are = q == 0 ? jv : (q == 2 ? -jv : 0.0);
-        const double aim = q == 1 ? -jv : (q == 3 ? jv : 0.0);
-        Tile<double> Dk;
-#pragma unroll
-        for (int r = 0; r < 4; ++r) {
-            const bool diag = 16 * L.TI + crow<double>(L.g, r) == 16 * L.TJ + L.j;
-            Dk.re[r] = fma(2.0, P.re[r], -D2.re[r]) + (diag ? are : 0.0);
-            Dk.im[r] = fma(2.0, P.im[r], -D2.im[r]) + (diag ? aim : 0.0);
-        }
-        if (k == 0) keep = D2;
-        D2 = D1;
-        D1 = Dk;
-    }
-    Tile<double> U;
-#pragma unroll
-    for (int r = 0; r < 4; ++r) {
-        U.re[r] = D1.re[r] - keep.re[r];
-        U.im[r] = D1.im[r] - keep.im[r];
-    }
-    return U;
-}
-
 template <class G, typename T>
 __device__ __forceinline__ Tile<T> square_n(Tile<T> U, int s, const Lane& L, double* s0) {
     for (int i = 0; i < s; ++i) {
@@ -964,6 +902,70 @@ __device__ __forceinline__ Tile<double> herm_mul(const Tile<double>& X, const Ti
         slot_store<G, double>(s1, Y, L);
         team_sync<G>();
         return slot_mul<G, double>(s0, s1, L);
+    }
+}
+
+// exp(-i theta X) for the (pre-scaled) Hermitian tile set X = G / theta,
+// spectrum in [-1, 1], by the degree-m Chebyshev series
+// J_0(theta) + 2 sum_{k>=1} (-i)^k J_k(theta) T_k(X) (eq. chebychev_series
+// with alpha = -theta, beta = theta, so the phase factor is 1), split into
+// its even and odd halves and returned in the Hermitian pair form C - i P of
+// the Taylor path.  With Y = T_2(X) = 2 X^2 - I, T_2j(X) = T_j(Y) and
+// T_{2j+1}(X) = X (2 sum_{i=1..j} (-1)^{j-i} T_i(Y) + (-1)^j I), so
+//   C = sum_{i <= m/2} e_i T_i(Y),   P = X sum_{i <= (m-1)/2} b_i T_i(Y),
+// e_0 = J_0, e_i = 2 (-1)^i J_2i, and b the alternating suffix sums of the
+// odd coefficients (row `ec` of the host's table: e, then b, kChebHalf
+// each).  The T_i(Y) follow from T_{i+1} = 2 Y T_i - T_{i-1}; every product
+// has the Hermitian left factor X or Y (registers on one-wave teams).
+// floor(m/2) + 1 products, where the Clenshaw recurrence in X takes m.  FP64.
+template <class G>
+__device__ void cheb_parts(const Tile<double>& Gt, int m, double theta, const double* ec, const Lane& L,
+                           double* s0, double* s1, Tile<double>& C, Tile<double>& P) {
+    const double inv = 1.0 / theta;
+    const double* eb = ec + kChebHalf;
+    const int qc = m / 2, qs = (m - 1) / 2;   // m >= 1
+    Tile<double> X, Sp;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const bool diag = 16 * L.TI + crow<double>(L.g, r) == 16 * L.TJ + L.j;
+        X.re[r] = Gt.re[r] * inv;
+        X.im[r] = Gt.im[r] * inv;
+        C.re[r] = diag ? ec[0] : 0.0;
+        Sp.re[r] = diag ? eb[0] : 0.0;
+        C.im[r] = Sp.im[r] = 0.0;
+    }
+    if (qc >= 1) {
+        Tile<double> Y = herm_mul<G>(X, X, L, s0, s1);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            const bool diag = 16 * L.TI + crow<double>(L.g, r) == 16 * L.TJ + L.j;
+            Y.re[r] = fma(2.0, Y.re[r], diag ? -1.0 : 0.0);
+            Y.im[r] *= 2.0;
+        }
+        axpy(C, ec[1], Y);
+        if (qs >= 1) axpy(Sp, eb[1], Y);
+        Tile<double> Tm = ident<double>(L), Tc = Y;
+        for (int i = 2; i <= qc; ++i) {
+            Tile<double> Tn = herm_mul<G>(Y, Tc, L, s0, s1);
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                Tn.re[r] = fma(2.0, Tn.re[r], -Tm.re[r]);
+                Tn.im[r] = fma(2.0, Tn.im[r], -Tm.im[r]);
+            }
+            axpy(C, ec[i], Tn);
+            if (i <= qs) axpy(Sp, eb[i], Tn);
+            Tm = Tc;
+            Tc = Tn;
+        }
+    }
+    if (qs >= 1) {
+        P = herm_mul<G>(X, Sp, L, s0, s1);
+    } else {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            P.re[r] = eb[0] * X.re[r];
+            P.im[r] = eb[0] * X.im[r];
+        }
     }
 }
 

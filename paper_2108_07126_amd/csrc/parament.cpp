@@ -732,7 +732,7 @@ bool pick_engine(int du, int precision, EngineInfo* out) {
     if (du <= 4) {
         e.kind = ENGINE_VALU;
         e.D = du <= 2 ? 2 : 4;
-        e.chunk_unit = 256;         // a run of a multiple of 4 slices per lane (two staging groups)
+        e.chunk_unit = 1024;        // a run of a multiple of 16 slices per lane (two sample blocks)
         e.chains_per_leaf = 4;      // a block of four waves is a leaf
         e.resident_chains = 256 * 8;
     } else {
@@ -1022,13 +1022,30 @@ pm_status pm_set_expm_method(pm_ctx* ctx, int method) {
     if (method == PM_EXPM_CHEBYSHEV && ctx->precision != PM_FP64)
         return fail(ctx, PM_E_UNSUPPORTED, "the Chebyshev series is built for PM_FP64 contexts only");
     if (method == PM_EXPM_CHEBYSHEV && !ctx->d_cheb) {
-        // coefficient table J_k(theta_m), k <= m, for every degree m
+        // coefficient table J_k(theta_m), k <= m, for every degree m; then
+        // the even/odd split of each degree's series (the tile engines):
+        // even e_0 = J_0, e_i = 2 (-1)^i J_2i, i <= m/2; odd, with
+        // o_j = 2 (-1)^j J_{2j+1} (j <= (m-1)/2) and the suffix sums
+        // s_i = o_i - s_{i+1}: b_0 = s_0, b_i = 2 s_i
         const double u = unit_roundoff(ctx->precision);
-        std::vector<double> tab((size_t)(pm::kMaxCheb + 1) * (pm::kMaxCheb + 1), 0.0);
+        constexpr int H = pm::kChebHalf;
+        std::vector<double> tab((size_t)pm::kChebSplitOffset + (size_t)(pm::kMaxCheb + 1) * 2 * H, 0.0);
         for (int m = 1; m <= pm::kMaxCheb; ++m) {
             const double th = chebyshev_theta(m, u);
-            for (int k = 0; k <= m; ++k)
-                tab[(size_t)m * (pm::kMaxCheb + 1) + k] = std::cyl_bessel_j((double)k, th);
+            double J[pm::kMaxCheb + 1];
+            for (int k = 0; k <= m; ++k) {
+                J[k] = std::cyl_bessel_j((double)k, th);
+                tab[(size_t)m * (pm::kMaxCheb + 1) + k] = J[k];
+            }
+            double* e = tab.data() + pm::kChebSplitOffset + (size_t)m * 2 * H;
+            double* b = e + H;
+            for (int i = 0; 2 * i <= m; ++i) e[i] = i == 0 ? J[0] : 2.0 * ((i & 1) ? -1.0 : 1.0) * J[2 * i];
+            const int qs = (m - 1) / 2;
+            double suf = 0.0;
+            for (int i = qs; i >= 0; --i) {
+                suf = 2.0 * ((i & 1) ? -1.0 : 1.0) * J[2 * i + 1] - suf;
+                b[i] = i == 0 ? suf : 2.0 * suf;
+            }
         }
         DeviceGuard g(ctx->device);
         void* ptr = nullptr;

@@ -13,6 +13,10 @@ constexpr int kMaxCtrl = 8;
 constexpr int kMaxBasis = 1 + 2 * kMaxCtrl + kMaxCtrl * (kMaxCtrl - 1) / 2;  // 45
 constexpr int kMaxDeg = PM_MAX_TAYLOR_DEGREE;
 constexpr int kMaxCheb = PM_MAX_CHEBYSHEV_DEGREE;
+// Chebyshev table: rows [m][k] = J_k(theta_m), k <= kMaxCheb, then for the
+// even/odd split rows [m][2][kChebHalf] of the even and odd coefficients.
+constexpr int kChebHalf = kMaxCheb / 2 + 1;
+constexpr int kChebSplitOffset = (kMaxCheb + 1) * (kMaxCheb + 1);
 constexpr int kOrderCF4 = PM_ORDER_CF4;   // two exponentials per slice, in product order
 constexpr int kOrderM6 = PM_ORDER_MAGNUS6; // sixth-order Magnus, three samples per slice
 constexpr int kFanIn = 8;                  // fan-in of the MFMA engines' product tree
@@ -41,7 +45,7 @@ struct PropParams {
     int basis_lds;               // MFMA engine: block keeps a copy of the basis in LDS
     int pair;                    // MFMA engine, D = 16: two slices of dimension <= 8 per tile
     int method;                  // PM_EXPM_TAYLOR or PM_EXPM_CHEBYSHEV
-    const double* cheb_j;        // Chebyshev: [m][k] = J_k(ctheta[m]), k <= m <= kMaxCheb
+    const double* cheb_j;        // Chebyshev: [m][k] = J_k(ctheta[m]), k <= m <= kMaxCheb; then the split rows
     double ctheta[kMaxCheb + 1]; // Chebyshev: half-width of the spectral interval for degree m
     uint8_t pair_a[kMaxBasis];   // order 4: control indices of i[H_a, H_b]
     uint8_t pair_b[kMaxBasis];

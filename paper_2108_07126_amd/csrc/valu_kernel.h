@@ -415,31 +415,45 @@ __device__ __forceinline__ SampleSet<ORD, KB> load_samples(const PropParams& p, 
     return s;
 }
 
-// Midpoint-rule samples of two consecutive slices a, a + 1 with one 16-byte
-// load per control (the pair (j, j + 1), j = min(a, last - 1), lies inside
-// the control's samples): half the load instructions, each lane touching
-// one line per control instead of two.  Slice a takes the first value of
-// the pair unless a >= last, when its sample (a == last) is the second; a
-// slice a + 1 past the end gets some sample and is not used.
-template <int KB>
-__device__ __forceinline__ void load_pair_ord2(const PropParams& p, int64_t a, int64_t last, SampleSet<2, KB>& s0,
-                                               SampleSet<2, KB>& s1) {
-    if (p.K == 0 || last == 0) {
-        s0 = load_samples<2, KB>(p, min(a, last));
-        s1 = s0;
+// Midpoint-rule samples (order 2) in blocks of SB consecutive slices per
+// lane.  A lane's slices are a contiguous run, `run` samples away from the
+// next lane's, so a load for one slice touches a different line in every
+// lane; issued slice by slice, each line is fetched again for every piece
+// of it once other traffic (the per-slice output) has evicted it in between.
+// Here a lane reads the SB samples of a control that its next SB slices
+// need at once, as SB / 2 contiguous 16-byte pieces, one block ahead of
+// their use.  Piece q holds the samples a, a + 1 (a = first + 2 q); a piece
+// that would pass the last sample is moved back to the last two, and a
+// slice past the end takes some sample (its exponent is zero).
+template <int KB, int SB>
+struct SampleBlock {
+    double v[KB][SB];
+};
+
+template <int KB, int SB>
+__device__ __forceinline__ void load_block(const PropParams& p, int64_t first, SampleBlock<KB, SB>& b) {
+    static_assert(SB % 2 == 0, "whole 16-byte pieces");
+    const int64_t S = p.n_samples;
+    if (p.K == 0 || S < 2) {
+        // no samples, or a single one (N = 1): every slice reads sample 0
+#pragma unroll
+        for (int k = 0; k < KB; ++k)
+#pragma unroll
+            for (int r = 0; r < SB; ++r) b.v[k][r] = p.K == 0 ? 0.0 : p.samples[(int64_t)min(k, p.K - 1) * S];
         return;
     }
-    const int64_t j = a < last ? a : last - 1;
-    const bool first = a < last;
-    const double* c = p.samples;
-    const int64_t S = p.n_samples;
 #pragma unroll
     for (int k = 0; k < KB; ++k) {
-        const int kk = min(k, p.K - 1);
-        struct alignas(8) Pair { double x, y; } v;
-        __builtin_memcpy(&v, c + (int64_t)kk * S + j, sizeof(v));
-        s0.v[k] = first ? v.x : v.y;
-        s1.v[k] = v.y;
+        const double* row = p.samples + (int64_t)min(k, p.K - 1) * S;
+#pragma unroll
+        for (int q = 0; q < SB / 2; ++q) {
+            const int64_t a = first + 2 * q;
+            const bool inner = a < S - 1;
+            struct alignas(8) Pair { double x, y; } v;
+            __builtin_memcpy(&v, row + (inner ? a : S - 2), sizeof(v));
+            b.v[k][2 * q] = inner ? v.x : v.y;
+            b.v[k][2 * q + 1] = v.y;
+        }
     }
 }
 
@@ -618,8 +632,8 @@ typedef unsigned v4u __attribute__((ext_vector_type(4)));
 template <typename T, int D>
 struct Stage {
     static constexpr int SB = D * D * 2 * (int)sizeof(T);   // bytes per slice
-    static constexpr int R = SB >= 128 ? 1 : 2;             // slices per segment (chains are
-                                                             // multiples of 2 R slices)
+    static constexpr int R = SB >= 128 ? 1 : 128 / SB;      // slices per segment: whole 128-byte
+                                                             // lines (R divides the runs' blocks)
     static constexpr int SEG = R * SB;
     static constexpr int STRIDE = SEG + 16;                  // padded against bank conflicts
     static constexpr int BUF = 64 * STRIDE;                  // bytes per wave
@@ -627,11 +641,22 @@ struct Stage {
 };
 
 // The phased slice e^{-i mu} (U or I + U) into this lane's staging row.
+// A wave whose slices all have mu = 0 (traceless Hamiltonians) skips the
+// rotation, which would multiply by exactly 1 and 0.
 template <int D, typename T>
-__device__ __forceinline__ void stage_phased(char* row, const Mat<D, T>& U, double mu, bool plus_ident) {
+__device__ __forceinline__ void stage_phased(char* row, const Mat<D, T>& U, double mu, bool plus_ident,
+                                             bool phased) {
+    T* out = reinterpret_cast<T*>(row);
+    if (!phased) {
+#pragma unroll
+        for (int e = 0; e < D * D; ++e) {
+            out[2 * e + 0] = (plus_ident && e % (D + 1) == 0) ? (T)((double)U.re[e] + 1.0) : U.re[e];
+            out[2 * e + 1] = U.im[e];
+        }
+        return;
+    }
     double sn, cs;
     phase_cs(mu, cs, sn);
-    T* out = reinterpret_cast<T*>(row);
 #pragma unroll
     for (int e = 0; e < D * D; ++e) {
         const double ur = (double)U.re[e] + ((plus_ident && e % (D + 1) == 0) ? 1.0 : 0.0);
@@ -710,7 +735,7 @@ propagate_valu(PropParams p) {
     __syncthreads();
     char* sbuf = stage_lds + wib * S::BUF;
     char* srow = sbuf + lane * S::STRIDE;
-    // a lane's run is a multiple of 4 (hence of 2 S::R) slices
+    // a lane's run is a multiple of 16 slices (two sample blocks, 2 S::R)
     const int64_t run = wave < p.n_chains ? p.chunk / 64 : 0;
     const int64_t base = wave * p.chunk + (int64_t)lane * run;
     const double lth = lane_theta_of(p, lane);
@@ -739,6 +764,7 @@ propagate_valu(PropParams p) {
         mu *= 1.0 / D;
 #pragma unroll
         for (int a = 0; a < D; ++a) g.re[hidx<D>(a, a)] -= mu;
+        const bool phased = __ballot(mu != 0.0) != 0;
         const double nu = (double)wave_max_f(norm1_bound<D>(g));
         int m, s;
         if (cheb) plan_cheb_lanes(p, nu, lane, lcth, m, s);
@@ -753,7 +779,7 @@ propagate_valu(PropParams p) {
             Mat<D, T> U = cheb ? exp_ch<D, T, EXP_CHEBYSHEV>(x, m, p.cheb_j + m * (kMaxCheb + 1), p.ctheta[m])
                                : exp_ch<D, T, EXP_TAYLOR>(x, m);
             for (int k = 0; k < s; ++k) U = mat_mul(U, U);
-            if constexpr (OUT == OUT_STAGED) stage_phased<D, T>(srow + r * S::SB, U, mu, false);
+            if constexpr (OUT == OUT_STAGED) stage_phased<D, T>(srow + r * S::SB, U, mu, false, phased);
             if constexpr (OUT == OUT_DIRECT)
                 if (valid) store_phased<D, T>(p, j, U, mu, false);
             mat_lmul_inplace<D, T>(U, Q);
@@ -772,7 +798,7 @@ propagate_valu(PropParams p) {
                 }
                 E = mat_convert<D, T>(Ed);
             }
-            if constexpr (OUT == OUT_STAGED) stage_phased<D, T>(srow + r * S::SB, E, mu, true);
+            if constexpr (OUT == OUT_STAGED) stage_phased<D, T>(srow + r * S::SB, E, mu, true, phased);
             if constexpr (OUT == OUT_DIRECT)
                 if (valid) store_phased<D, T>(p, j, E, mu, true);
             const Mat<D, T> P = mat_mul(E, mat_convert<D, T>(Qx));
@@ -784,48 +810,114 @@ propagate_valu(PropParams p) {
         }
         phi += mu;
     };
-    // R slices of the run (from step i0) with the samples in `cur`, then
-    // the staged output of those R slices.
-    auto group = [&](const SampleSet<ORD, KB> (&cur)[S::R], int64_t i0) {
-#pragma unroll
-        for (int r = 0; r < S::R; ++r) step(cur[r], base + i0 + r, r);
+    // The staged output of the R slices of the run that end at step i1.
+    auto flush = [&](int64_t i1) {
         if constexpr (OUT == OUT_STAGED) {
             wave_lds_sync();
-            flush_stage<T, D>(p, sbuf, wave * p.chunk + i0, run, lane);
+            flush_stage<T, D>(p, sbuf, wave * p.chunk + i1 - S::R, run, lane);
             wave_lds_sync();
         }
     };
-    auto load_group = [&](SampleSet<ORD, KB> (&dst)[S::R], int64_t i0) {
-        if constexpr (ORD == 2 && S::R == 2) {
-            load_pair_ord2<KB>(p, base + i0, last, dst[0], dst[1]);
-        } else {
+    if constexpr (ORD == 2) {
+        // Samples in blocks of SB slices, one block ahead (load_block): the
+        // FP64 two-dimensional kernel with output runs its blocks unrolled
+        // (UNR), everything else one slice per pass of a loop.  Blocks of 8
+        // (64 bytes per control) where the controls are few; 4 in the
+        // unrolled kernel, whose 16 unrolled slices of 8 would hold more
+        // registers.
+        constexpr bool UNR = D == 2 && kF64 && OUT == OUT_STAGED;
+        constexpr int SB0 = KB > 2 ? 2 : (UNR ? 4 : 8);
+        constexpr int SB = (OUT == OUT_STAGED && SB0 < S::R) ? S::R : SB0;
+        static_assert(OUT != OUT_STAGED || SB % S::R == 0, "segments inside a block");
+        using Blk = SampleBlock<KB, SB>;
+        auto slice_of = [&](const Blk& b, int r) {
+            SampleSet<2, KB> x;
 #pragma unroll
-            for (int r = 0; r < S::R; ++r) dst[r] = load_samples<ORD, KB>(p, min(base + i0 + r, last));
-        }
-    };
-    if constexpr (D == 2) {
-        // Samples travel one group ahead in two alternating register sets:
-        // the loads for a group are issued before the previous group's output
-        // stores, so waiting for them never waits for those stores.
-        SampleSet<ORD, KB> A[S::R], B[S::R];
-        load_group(A, 0);
-        if constexpr (OUT == OUT_STAGED) dummy_flush<T, D>(p, lane);
-        for (int64_t i0 = 0; i0 < run; i0 += 2 * S::R) {
-            load_group(B, i0 + S::R);
-            group(A, i0);
-            load_group(A, i0 + 2 * S::R);
-            group(B, i0 + S::R);
+            for (int k = 0; k < KB; ++k) x.v[k] = b.v[k][r];
+            return x;
+        };
+        if constexpr (UNR) {
+            // Two blocks in alternating registers, each run straight through:
+            // a block's loads are issued before the previous block's output
+            // stores, so waiting for them never waits for those stores (the
+            // zero-length stores before the loop give its first pass the
+            // same count of younger stores as every later pass).
+            auto block = [&](const Blk& b, int64_t i0) {
+#pragma unroll
+                for (int r = 0; r < SB; ++r) {
+                    step(slice_of(b, r), base + i0 + r, r % S::R);
+                    if ((r + 1) % S::R == 0) flush(i0 + r + 1);
+                    // the slices' exponentials are independent: keep the
+                    // scheduler from overlapping them (their registers
+                    // would spill)
+                    __builtin_amdgcn_sched_barrier(0);
+                }
+            };
+            Blk A, B;
+            load_block<KB, SB>(p, base, A);
+            if constexpr (OUT == OUT_STAGED)
+#pragma unroll
+                for (int q = 0; q < SB / S::R; ++q) dummy_flush<T, D>(p, lane);
+            for (int64_t i0 = 0; i0 < run; i0 += 2 * SB) {
+                load_block<KB, SB>(p, base + i0 + SB, B);
+                block(A, i0);
+                load_block<KB, SB>(p, base + i0 + 2 * SB, A);
+                block(B, i0 + SB);
+            }
+        } else {
+            // One slice per pass of a loop (D = 4: an unrolled block would
+            // not fit the instruction cache; D = 2 without output or in FP32:
+            // as fast, fewer registers); the current block shifts down by one
+            // slot per slice and takes over the next block, loaded a block
+            // earlier, when it is used up.
+            Blk A, B;
+            load_block<KB, SB>(p, base, A);
+            load_block<KB, SB>(p, base + SB, B);
+            for (int64_t i = 0; i < run; ++i) {
+                const SampleSet<2, KB> cur = slice_of(A, 0);
+#pragma unroll
+                for (int k = 0; k < KB; ++k)
+#pragma unroll
+                    for (int r = 0; r + 1 < SB; ++r) A.v[k][r] = A.v[k][r + 1];
+                step(cur, base + i, (int)(i % S::R));
+                if ((i + 1) % S::R == 0) flush(i + 1);
+                if ((i + 1) % SB == 0) {
+                    A = B;
+                    load_block<KB, SB>(p, base + i + 1 + SB, B);
+                }
+            }
         }
     } else {
-        // D = 4 keeps one sample set in flight (the unrolled pair of slices
-        // would not fit the register file); S::R = 1 here.
-        SampleSet<ORD, KB> A[S::R];
-        load_group(A, 0);
-        for (int64_t i0 = 0; i0 < run; i0 += S::R) {
-            const SampleSet<ORD, KB> cur = A[0];
-            load_group(A, i0 + S::R);
-            const SampleSet<ORD, KB> C[S::R] = {cur};
-            group(C, i0);
+        // Orders 4 and CF4: R slices' samples per group, one group ahead.
+        auto group = [&](const SampleSet<ORD, KB> (&cur)[S::R], int64_t i0) {
+#pragma unroll
+            for (int r = 0; r < S::R; ++r) step(cur[r], base + i0 + r, r);
+            flush(i0 + S::R);
+        };
+        auto load_group = [&](SampleSet<ORD, KB> (&dst)[S::R], int64_t i0) {
+#pragma unroll
+            for (int r = 0; r < S::R; ++r) dst[r] = load_samples<ORD, KB>(p, min(base + i0 + r, last));
+        };
+        if constexpr (D == 2) {
+            SampleSet<ORD, KB> A[S::R], B[S::R];
+            load_group(A, 0);
+            if constexpr (OUT == OUT_STAGED) dummy_flush<T, D>(p, lane);
+            for (int64_t i0 = 0; i0 < run; i0 += 2 * S::R) {
+                load_group(B, i0 + S::R);
+                group(A, i0);
+                load_group(A, i0 + 2 * S::R);
+                group(B, i0 + S::R);
+            }
+        } else {
+            // D = 4 keeps one sample set in flight; S::R = 1 here.
+            SampleSet<ORD, KB> A[S::R];
+            load_group(A, 0);
+            for (int64_t i0 = 0; i0 < run; i0 += S::R) {
+                const SampleSet<ORD, KB> cur = A[0];
+                load_group(A, i0 + S::R);
+                const SampleSet<ORD, KB> C[S::R] = {cur};
+                group(C, i0);
+            }
         }
     }
     if constexpr (kF64) Qx = Q;

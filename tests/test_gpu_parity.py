@@ -134,12 +134,13 @@ def test_forced_and_large_norm_squarings(pm, d):
 def test_chunking_and_tree_shape_invariance(pm, d):
     """Chain lengths 1 (pure tree), ragged and large give the same U(T); the
     same configuration twice is bitwise identical."""
-    w = synth.random_system(d, 2, n_slices=1333, h=0.03, order=2, tag=4)
-    ref = run(pm, w, chunk=64 if d <= 4 else 7)
-    for ch in ((64, 128, 1344) if d <= 4 else (1, 64, 1333)):
+    # dimensions <= 4 take chains in whole units of 1024 slices
+    w = synth.random_system(d, 2, n_slices=9333 if d <= 4 else 1333, h=0.03, order=2, tag=4)
+    ref = run(pm, w, chunk=1024 if d <= 4 else 7)
+    for ch in ((2048, 3072, 10240) if d <= 4 else (1, 64, 1333)):
         U = run(pm, w, chunk=ch)
         assert orc.relative_frobenius(U, ref) <= 1e-13
-    again = run(pm, w, chunk=64 if d <= 4 else 7)
+    again = run(pm, w, chunk=1024 if d <= 4 else 7)
     assert np.array_equal(again, ref)
 
 
@@ -178,11 +179,11 @@ def test_small_dims_deep_tree(pm, d):
     """The small-dimension engine with about 150 leaves (three levels of the
     fan-in-8 tree, a ragged last group and a ragged last chain) against the
     oracle, and against a shallower split of the same slices."""
-    w = synth.random_system(d, 2, n_slices=150_001, h=0.01, order=2, tag=70 + d)
+    w = synth.random_system(d, 2, n_slices=600_001, h=0.01, order=2, tag=70 + d)
     Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 2)
-    U = run(pm, w, chunk=256)
+    U = run(pm, w, chunk=1024)
     assert orc.relative_frobenius(U, Uo) <= TOL64
-    assert orc.relative_frobenius(run(pm, w, chunk=8192), U) <= 1e-12
+    assert orc.relative_frobenius(run(pm, w, chunk=32768), U) <= 1e-12
 
 
 def test_state_machine_and_errors(pm):
