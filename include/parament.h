@@ -116,8 +116,10 @@ typedef enum pm_precision {
 /* How the slice exponentials are evaluated (Matrix exponential section). */
 typedef enum pm_expm_method {
     PM_EXPM_TAYLOR = 0,    /* truncated Taylor series with scaling and squaring (default) */
-    PM_EXPM_CHEBYSHEV = 1  /* the paper's Chebyshev series (eq. chebychev_series), Clenshaw
-                              recurrence (Algorithm 1), with scaling and squaring */
+    PM_EXPM_CHEBYSHEV = 1  /* the paper's Chebyshev series (eq. chebychev_series) with
+                              scaling and squaring; dimensions <= 4 by the Clenshaw
+                              recurrence (Algorithm 1) in the algebra of G, larger ones
+                              split into even and odd halves over T_i(2X^2 - I) */
 } pm_expm_method;
 
 /* Create a context on HIP device `device` computing in `precision`.
@@ -186,8 +188,9 @@ pm_status pm_equiprop_dev_noalloc(pm_ctx *ctx, const double *samples_dev,
  * Applications and outlook section).  For a real loss L of U(T) with
  * dL = Re Tr(W^H dU(T)) -- W is 2 dL/d conj(U), the convention of PyTorch's
  * complex gradients -- writes dL/d samples into grad_dev (float64
- * [n_ctrl][n_samples]).  Runs its own forward pass (U(T) also copied to
- * U_out_dev when non-NULL, complex128 [dim][dim]) keeping one checkpoint
+ * [n_ctrl][n_samples]).  Runs its own forward pass (U(T) written to
+ * U_out_dev when non-NULL, complex128 [dim][dim], which must not overlap
+ * W_dev, samples or grad_dev; the backward pass reads it there) keeping one checkpoint
  * product per chain of consecutive slices (see pm_set_chunk) and the product
  * tree's nodes, then a backward pass that recomputes each chain's slice
  * propagators from its checkpoint and contracts the Frechet derivatives of
@@ -365,8 +368,10 @@ pm_status pm_workspace_plan(int64_t dim, int64_t n_ctrl, int order, int precisio
 /* Choose the exponential (pm_expm_method) for pm_equiprop / pm_equiprop_dev.
  * PM_EXPM_CHEBYSHEV: per slice, with nu = ||G_j||_1 (the spectrum lies in
  * [-nu, nu]), the planner picks the degree m <= PM_MAX_CHEBYSHEV_DEGREE and
- * squarings s minimising m + s (Clenshaw takes m products) with
- * nu / 2^s <= theta_m, theta_m from pm_chebyshev_theta; the series is taken
+ * squarings s minimising P(m) + s with nu / 2^s <= theta_m, P(m) = 0, 1 and
+ * floor(m/2) + 1 for m = 1, 2 and m >= 3 (the products of the even/odd split
+ * evaluation), ties to the smaller s, then the smaller m; theta_m from
+ * pm_chebyshev_theta; the series is taken
  * on the interval [-theta_m, theta_m] (it contains the scaled spectrum), so
  * its coefficients a_k = (-i)^k J_k(theta_m) depend on m only.  Dimensions
  * <= 4 first shift G by tr G / D.  PM_FP64 contexts only (PM_E_UNSUPPORTED

@@ -37,6 +37,7 @@ __device__ void run_packet(const BatchParams& bp, const BatchPacket& P, double* 
     L.wt = wave % G::TW;
     L.TI = L.wt / G::TD;
     L.TJ = L.wt % G::TD;
+    L.ks = (p.du + 3) / 4;   // the tiles vanish outside the instance's du x du block
     double* s0 = slots + team * 2 * G::SLOT;
     double* s1 = s0 + G::SLOT;
     double* tred = red + team * G::TD * D;

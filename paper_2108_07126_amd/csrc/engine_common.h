@@ -167,10 +167,12 @@ __device__ __forceinline__ void plan_expm_lanes(const PropParams& p, double nu, 
     s_out = (key >> 5) & 63;
 }
 
-// Chebyshev planner (Clenshaw takes m products): lane l tests degree l + 1
-// against its interval half-width (preloaded in lane_ctheta, +inf past the
-// last degree); minimise m + s, ties to the smaller s.  With force_s >= 0
-// the smallest feasible degree (the largest if none is).
+// Chebyshev planner: lane l tests degree l + 1 against its interval
+// half-width (preloaded in lane_ctheta, +inf past the last degree) and
+// minimises the products of the even/odd split evaluation plus the
+// squarings (the Taylor count taylor_products(m) + s), ties to the smaller s,
+// then to the smaller degree.  With force_s >= 0 the smallest feasible
+// degree (the largest if none is).
 __device__ __forceinline__ double lane_ctheta_of(const PropParams& p, int lane) {
     return lane < kMaxCheb ? p.ctheta[lane + 1] : __builtin_inf();
 }
@@ -190,7 +192,7 @@ __device__ __forceinline__ void plan_cheb_lanes(const PropParams& p, double nu, 
         return;
     }
     const int s = min(min_squarings(nu, cand ? lane_ctheta : 1.0), 63);
-    const int key = min2rows(cand ? ((lane + 1 + s) << 12) | (s << 6) | lane : 0x7fffffff);
+    const int key = min2rows(cand ? ((taylor_products(lane + 1) + s) << 12) | (s << 6) | lane : 0x7fffffff);
     m_out = (key & 63) + 1;
     s_out = (key >> 6) & 63;
 }

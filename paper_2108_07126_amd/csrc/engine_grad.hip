@@ -207,7 +207,7 @@ __device__ void pair_taylor(const Tile<double>& Gt, const Tile<double>& Et, int 
 // Hermitian (G, and the powers of Y = G^2) are taken straight from registers
 // (reg_mul_herm); the three with a general left factor (E G, dP Y, E S') are
 // staged as before.  Same series, same products.
-template <class G>
+template <class G, int KS = 4>
 __device__ void pair_taylor_reg(const Tile<double>& Gt, const Tile<double>& Et, int m, const Lane& L,
                                 double* s0, double* s1, Tile<double>& U, Tile<double>& dU) {
     Tile<double> C = ident<double>(L), dC = tzero(), S, dS;
@@ -216,8 +216,8 @@ __device__ void pair_taylor_reg(const Tile<double>& Gt, const Tile<double>& Et, 
         dS = Et;
     } else {
         const int qc = m / 2, qs = (m - 1) / 2;
-        const Tile<double> Y = reg_mul_herm<double>(Gt, Gt);
-        const Tile<double> dY = tadd(reg_mul_herm<double>(Gt, Et), mul2<G>(Et, Gt, L, s0, s1));
+        const Tile<double> Y = reg_mul_herm<double, 0, false, KS>(Gt, Gt);
+        const Tile<double> dY = tadd(reg_mul_herm<double, 0, false, KS>(Gt, Et), mul2<G>(Et, Gt, L, s0, s1));
         Tile<double> Sp = ident<double>(L), dSp = tzero();
         axpy(C, cos_coef(1), Y);
         axpy(dC, cos_coef(1), dY);
@@ -227,8 +227,8 @@ __device__ void pair_taylor_reg(const Tile<double>& Gt, const Tile<double>& Et, 
         }
         Tile<double> P = Y, dP = dY;
         for (int k = 2; k <= qc; ++k) {
-            const Tile<double> Pn = reg_mul_herm<double>(P, Y);
-            const Tile<double> t1 = reg_mul_herm<double>(P, dY);   // P dY
+            const Tile<double> Pn = reg_mul_herm<double, 0, false, KS>(P, Y);
+            const Tile<double> t1 = reg_mul_herm<double, 0, false, KS>(P, dY);   // P dY
             const Tile<double> t2 = mul2<G>(dP, Y, L, s0, s1);     // dP Y
             P = Pn;
             dP = tadd(t1, t2);
@@ -240,8 +240,8 @@ __device__ void pair_taylor_reg(const Tile<double>& Gt, const Tile<double>& Et, 
             }
         }
         if (qs >= 1) {
-            S = reg_mul_herm<double>(Gt, Sp);
-            dS = tadd(reg_mul_herm<double>(Gt, dSp), mul2<G>(Et, Sp, L, s0, s1));   // G dS' + E S'
+            S = reg_mul_herm<double, 0, false, KS>(Gt, Sp);
+            dS = tadd(reg_mul_herm<double, 0, false, KS>(Gt, dSp), mul2<G>(Et, Sp, L, s0, s1));   // G dS' + E S'
         } else {
             S = Gt;
             dS = Et;
@@ -253,12 +253,12 @@ __device__ void pair_taylor_reg(const Tile<double>& Gt, const Tile<double>& Et, 
 
 // U_j = exp(-i G) from the scaled exponent Gt by the series and s squarings
 // (one-wave teams: the series in registers).
-template <class G>
+template <class G, int KS = 4>
 __device__ __forceinline__ Tile<double> slice_exp(const Tile<double>& Gt, int m, int s, const Lane& L, double* s0,
                                                   double* s1) {
     if constexpr (G::TW == 1) {
         Tile<double> C, P;
-        taylor_parts_reg<double>(Gt, m, L, C, P);
+        taylor_parts_reg<double, 0, false, false, KS>(Gt, m, L, C, P);
         return square_n<G, double>(combine_cp<double>(C, P), s, L, s0);
     } else {
         return square_n<G, double>(taylor_exp<G, double>(Gt, m, L, s0, s1), s, L, s0);
@@ -345,6 +345,7 @@ backward_mfma(GradParams gp) {
     L.wt = wave % G::TW;
     L.TI = L.wt / G::TD;
     L.TJ = L.wt % G::TD;
+    L.ks = (p.du + 3) / 4;   // the tiles vanish outside the leading du x du block
     double* s0 = slots + team * 2 * G::SLOT;
     double* s1 = s0 + G::SLOT;
     if constexpr (BL) {
@@ -455,6 +456,236 @@ backward_mfma(GradParams gp) {
     }
 }
 
+// The backward of one-wave teams (D = 16) as a two-stage pipeline: each
+// unit (a chain, or a part of one) runs on two waves of the block.  The
+// first (role 0) carries the recursion: slice j's exponent and plan,
+// U_j, Lambda_j = Omega_j U_j^H and Omega_{j+1} = U_j Lambda_j, and hands
+// (G_j scaled, Lambda_j, m, s) to the second through LDS.  The second
+// (role 1) takes F_j = L_f(G_j, Lambda_j) by the (value, derivative) series
+// and its contractions with the basis, for slice j while the first is at
+// slice j + 1: per slice the longer of the two instead of their sum.  Before
+// the slices, role 0 multiplies the checkpoint's tree nodes while role 1
+// multiplies the block's earlier chains and forms Z = W^H U(T).  Same
+// products as backward_mfma; the block's waves meet at two barriers per
+// slice, all the same number of times (units past the end idle through them).
+template <int NT, bool BL, int KS>
+__global__ void __launch_bounds__(64 * NT) __attribute__((amdgpu_waves_per_eu(2, 8)))
+backward_pipe(GradParams gp) {
+    using G = Geo<16, NT>;   // G::NT: chains per leaf of the forward's tree
+    static_assert(NT % 2 == 0, "two waves per unit");
+    const PropParams& p = gp.p;
+    extern __shared__ double dsm[];
+    double* slots = dsm;
+    double* red = slots + NT * 2 * G::SLOT;
+    double* lbasis = red + G::TD * 16 + 2;
+    double* hand = lbasis + (BL ? p.M * 512 : 0);    // per unit: 2 tiles of 512 doubles, then m, s
+
+    Lane L;
+    L.lane = threadIdx.x & 63;
+    L.g = L.lane >> 4;
+    L.j = L.lane & 15;
+    L.wt = 0;
+    L.TI = L.TJ = 0;
+    L.ks = (p.du + 3) / 4;   // the tiles vanish outside the leading du x du block
+    const int wave = wave_uniform((int)(threadIdx.x >> 6));
+    const int role = wave & 1;
+    double* s0 = slots + wave * 2 * G::SLOT;
+    double* s1 = s0 + G::SLOT;
+    if constexpr (BL) {
+        const int n = p.M * 512;
+        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
+    }
+    __syncthreads();
+    const double* bas = BL ? lbasis : p.basis;
+    double* hb = hand + (wave >> 1) * 1040;
+    int* hms = reinterpret_cast<int*>(hb + 1024);
+    // lane-private handoff layout: tile t, register r of lane l at t * 512 + r * 64 + l (re), + 256 (im)
+    auto put = [&](int t, const Tile<double>& x) {
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            hb[t * 512 + r * 64 + L.lane] = x.re[r];
+            hb[t * 512 + 256 + r * 64 + L.lane] = x.im[r];
+        }
+    };
+    auto get = [&](int t) {
+        Tile<double> x;
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            x.re[r] = hb[t * 512 + r * 64 + L.lane];
+            x.im[r] = hb[t * 512 + 256 + r * 64 + L.lane];
+        }
+        return x;
+    };
+
+    const int64_t unit = (int64_t)blockIdx.x * (NT / 2) + (wave >> 1);
+    const int64_t chain = unit / gp.split;
+    const int64_t part = unit % gp.split;
+    const bool live = chain < p.n_chains;
+    const int64_t c0 = live ? chain * p.chunk : 0, c1 = live ? min(p.n_slices, c0 + p.chunk) : 0;
+    const int64_t sub = (p.chunk + gp.split - 1) / gp.split;   // slices per unit (block-uniform bound)
+    const int64_t j0 = min(c1, c0 + part * sub);
+    const int64_t j1 = live ? min(c1, j0 + sub) : j0;
+
+    const WeightRecipe wr = weight_recipe(p, L.lane);
+    const double lth = lane_theta_of(p, L.lane);
+    const int64_t bofs = mfma_basis_index(16, 0, 0, 0, 0, 0, L.lane);
+    auto slice_exponent = [&](const SliceSamples& smp, Tile<double>& Gt, int& m, int& s) {
+        const double wl = combine_weight(p, wr, smp);
+        double gre[4] = {0, 0, 0, 0}, gim[4] = {0, 0, 0, 0};
+#pragma unroll 4
+        for (int mm = 0; mm < p.M; ++mm) {
+            const double w = readlane_d(wl, mm);
+            const double* bb = bas + bofs + (int64_t)mm * 512;
+#pragma unroll
+            for (int r = 0; r < 4; ++r) {
+                gre[r] = fma(w, bb[r * 64], gre[r]);
+                gim[r] = fma(w, bb[256 + r * 64], gim[r]);
+            }
+        }
+        const double nu = wave_uniform(team_norm1<G, double>(gre, gim, L, red));
+        plan_expm_lanes(p, nu, L.lane, lth, m, s);
+        m = wave_uniform(m);
+        s = wave_uniform(s);
+#pragma unroll
+        for (int r = 0; r < 4; ++r) {
+            Gt.re[r] = ldexp(gre[r], -s);
+            Gt.im[r] = ldexp(gim[r], -s);
+        }
+    };
+
+    // checkpoint P = U_{j0-1} ... U_0 (chain_checkpoint's product, in two
+    // halves) and Omega_{j0} = P Z P^H
+    Tile<double> Om, P;
+    const int64_t NN = 512;
+    const int64_t b = chain / G::NT;   // the chain's leaf
+    if (role == 0) {
+        if (live) {
+            // the aligned tree nodes above level 0 before the leaf's group
+            P = ident<double>(L);
+            int nlev = 0;
+            for (int64_t cnt = p.n_leaves; cnt > 1; cnt = (cnt + kFanIn - 1) / kFanIn) ++nlev;
+            for (int l = nlev; l >= 1; --l) {
+                const int64_t d = (b >> (kFanInLog2 * l)) & (kFanIn - 1);
+                if (d == 0) continue;
+                int64_t off = 0, cnt = p.n_leaves;
+                for (int q = 0; q < l; ++q) {
+                    off += cnt;
+                    cnt = (cnt + kFanIn - 1) / kFanIn;
+                }
+                const int64_t first = (b >> (kFanInLog2 * (l + 1))) << kFanInLog2;
+                // four nodes in flight at a time
+#pragma unroll
+                for (int h = 0; h < kFanIn; h += kFanIn / 2) {
+                    Tile<double> X[kFanIn / 2];
+#pragma unroll
+                    for (int q = 0; q < kFanIn / 2; ++q)
+                        if (h + q < d) X[q] = node_load<G>(p.nodes + (off + first + h + q) * NN, L);
+#pragma unroll
+                    for (int q = 0; q < kFanIn / 2; ++q)
+                        if (h + q < d) P = mul2<G>(X[q], P, L, s0, s1);
+                }
+            }
+        }
+    } else if (live) {
+        // the level-0 nodes before the leaf in its group, then the leaf's
+        // earlier chains (later on the left), and Z = W^H U(T)
+        Tile<double> Pc = ident<double>(L);
+        const int64_t d0 = b & (kFanIn - 1), first0 = b - d0;
+        for (int64_t q = 0; q < d0; ++q) Pc = mul2<G>(node_load<G>(p.nodes + (first0 + q) * NN, L), Pc, L, s0, s1);
+        for (int64_t c = b * G::NT; c < chain; ++c)
+            Pc = mul2<G>(node_load<G>(p.chain_out + c * NN, L), Pc, L, s0, s1);
+        const Tile<double> Wt = load_user<G>(gp.W, p.du, 0.0, L);
+        const Tile<double> UTt = load_user<G>(gp.UT, p.du, 1.0, L);
+        put(0, Pc);
+        put(1, mul_adjA<G>(Wt, UTt, L, s0, s1));
+    }
+    __syncthreads();
+    SliceSamples smp;
+    if (role == 0 && live) {
+        P = mul2<G>(get(0), P, L, s0, s1);
+        const Tile<double> Z = get(1);
+        // the unit's predecessors in the chain, recomputed
+        for (int64_t j = c0; j < j0; ++j) {
+            Tile<double> Gt;
+            int m, s;
+            slice_exponent(gather_samples(p, wr, j), Gt, m, s);
+            P = mul2<G>(slice_exp<G, KS>(Gt, m, s, L, s0, s1), P, L, s0, s1);
+        }
+        Om = mul_adjB<G>(mul2<G>(P, Z, L, s0, s1), P, L, s0, s1);
+        smp = gather_samples(p, wr, j0 < j1 ? j0 : 0);
+    }
+    __syncthreads();   // role 1 has read nothing yet; role 0 is done with the handoff area
+
+    // the pipeline: step k, role 0 on slice j0 + k, role 1 on slice j0 + k - 1.
+    // One loop per role (the other role's loop-carried state stays out of
+    // its registers); both take sub + 1 steps of two barriers each.
+    if (role == 0) {
+        for (int64_t k = 0; k <= sub; ++k) {
+            const int64_t j = j0 + k;
+            const bool act = j < j1 && k < sub;
+            Tile<double> Gt, Lam;
+            int m = 0, s = 0;
+            if (act) {
+                const SliceSamples cur = smp;
+                if (j + 1 < j1) smp = gather_samples(p, wr, j + 1);
+                slice_exponent(cur, Gt, m, s);
+                Tile<double> Cr, Pr;
+                taylor_parts_reg<double, 0, false, false, KS>(Gt, m, L, Cr, Pr);
+                const Tile<double> U = square_n<G, double>(combine_cp<double>(Cr, Pr), s, L, s0);
+                Lam = mul_adjB<G>(Om, U, L, s0, s1);
+                Om = s == 0 ? reg_mul_cp<double, 0, false, KS>(Cr, Pr, Lam) : mul2<G>(U, Lam, L, s0, s1);
+            }
+            __syncthreads();
+            if (act) {
+                put(0, Gt);
+                put(1, Lam);
+                if (L.lane == 0) {
+                    hms[0] = m;
+                    hms[1] = s;
+                }
+            }
+            __syncthreads();
+        }
+    } else {
+        Tile<double> Gt, Lam;
+        int m = 0, s = 0;
+        for (int64_t k = 0; k <= sub; ++k) {
+            const int64_t j = j0 + k - 1;
+            if (k >= 1 && j < j1) {
+                // F_j = L_f(G_j, Lambda_j) and dL/dw_{j,m} = Re Tr(F_j B_m)
+                Tile<double> Up, F;
+                pair_taylor_reg<G, KS>(Gt, tscale(Lam, -s), m, L, s0, s1, Up, F);
+                for (int q = 0; q < s; ++q) {
+                    team_sync<G>();
+                    slot_store<G, double>(s0, Up, L);
+                    slot_store<G, double>(s1, F, L);
+                    team_sync<G>();
+                    const Tile<double> Un = slot_mul<G, double>(s0, s0, L);
+                    F = tadd(slot_mul<G, double>(s0, s1, L), slot_mul<G, double>(s1, s0, L));
+                    Up = Un;
+                }
+                for (int mm = 0; mm < p.M; ++mm) {
+                    const double* bb = bas + bofs + (int64_t)mm * 512;
+                    double acc = 0.0;
+#pragma unroll
+                    for (int r = 0; r < 4; ++r) acc = fma(F.re[r], bb[r * 64], fma(F.im[r], bb[256 + r * 64], acc));
+                    const double g = team_sum<G>(acc, L, red);
+                    if (L.lane == 0) {
+                        gp.gw[j * p.M + mm] = g;
+                        if (gp.grad_direct && mm >= 1) gp.grad_direct[(int64_t)(mm - 1) * p.n_samples + j] = p.h * g;
+                    }
+                }
+            }
+            __syncthreads();
+            __syncthreads();
+            Gt = get(0);
+            Lam = get(1);
+            m = hms[0];
+            s = hms[1];
+        }
+    }
+}
+
 // Rows < rows and columns < cols of a tile set from a row-major complex
 // block with leading dimension ld (zero elsewhere).
 template <class G>
@@ -511,6 +742,7 @@ trajectory_mfma(TrajParams tp) {
     L.wt = wave % G::TW;
     L.TI = L.wt / G::TD;
     L.TJ = L.wt % G::TD;
+    L.ks = (tp.p.du + 3) / 4;   // the tiles vanish outside the leading du x du block
     double* s0 = slots + team * 2 * G::SLOT;
     double* s1 = s0 + G::SLOT;
     if constexpr (BL) {
@@ -665,6 +897,30 @@ hipError_t launch_bwd(const GradParams& gp, size_t lds, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// KS: register products over the k-slices that the embedded dimension
+// reaches (1 for du <= 4, 2 for du <= 8, else all 4).
+template <bool BL, int KS>
+hipError_t launch_bwd_pipe(const GradParams& gp, size_t lds, hipStream_t stream) {
+    constexpr int NT = 4;   // two units of two waves per block
+    static bool attr_set = false;
+    if (!attr_set) {
+        hipError_t e = hipFuncSetAttribute((const void*)backward_pipe<NT, BL, KS>,
+                                           hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
+        if (e != hipSuccess) return e;
+        attr_set = true;
+    }
+    const int64_t units = gp.p.n_chains * gp.split;
+    const int64_t blocks = (units + NT / 2 - 1) / (NT / 2);
+    hipLaunchKernelGGL((backward_pipe<NT, BL, KS>), dim3((unsigned)blocks), dim3(64 * NT), lds, stream, gp);
+    return hipGetLastError();
+}
+
+template <bool BL>
+hipError_t launch_bwd_pipe_ks(const GradParams& gp, size_t lds, hipStream_t stream) {
+    if (gp.p.du <= 4) return launch_bwd_pipe<BL, 1>(gp, lds, stream);
+    return gp.p.du <= 8 ? launch_bwd_pipe<BL, 2>(gp, lds, stream) : launch_bwd_pipe<BL, 4>(gp, lds, stream);
+}
+
 template <int D, int NT, bool BL>
 hipError_t launch_traj(const TrajParams& tp, size_t lds, hipStream_t stream) {
     static bool attr_set = false;
@@ -705,16 +961,21 @@ hipError_t launch_backward(int D, const GradParams& gp, double* grad_samples, hi
     const bool bl = gp.p.basis_lds != 0;
     if (bl) lds += sizeof(double) * (size_t)gp.p.M * TD * TD * 512;
     hipError_t e;
+    // D = 16: the two-wave pipeline, with a handoff area of 1040 doubles per
+    // unit; at order 2 it also writes dL/d samples itself
+    const size_t lds_pipe = lds + sizeof(double) * 1040 * 2;
+    GradParams gq = gp;
+    gq.grad_direct = (D == 16 && gp.p.order == 2) ? grad_samples : nullptr;
     switch (D) {
-        case 16: e = bl ? launch_bwd<16, 4, true>(gp, lds, stream) : launch_bwd<16, 4, false>(gp, lds, stream); break;
+        case 16: e = bl ? launch_bwd_pipe_ks<true>(gq, lds_pipe, stream) : launch_bwd_pipe_ks<false>(gq, lds_pipe, stream); break;
         case 32: e = launch_bwd<32, 1, false>(gp, lds, stream); break;
         case 64: e = launch_bwd<64, 1, false>(gp, lds, stream); break;
         default: return hipErrorInvalidValue;
     }
     if (e != hipSuccess) return e;
     const int64_t n = (int64_t)gp.p.K * gp.p.n_samples;
-    if (n == 0) return hipSuccess;
-    hipLaunchKernelGGL(samples_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, gp,
+    if (n == 0 || gq.grad_direct) return hipSuccess;
+    hipLaunchKernelGGL(samples_grad, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, stream, gq,
                        grad_samples);
     return hipGetLastError();
 }

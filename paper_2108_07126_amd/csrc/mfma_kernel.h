@@ -75,6 +75,9 @@ propagate_mfma(PropParams p) {
     L.wt = wave % G::TW;
     L.TI = L.wt / G::TD;
     L.TJ = L.wt % G::TD;
+    // staged products over the rows that the embedded dimension reaches
+    // (slice pairs use both diagonal blocks)
+    if constexpr (!PAIR) L.ks = (p.du + 3) / 4;
     double* s0 = slots + team * 2 * G::SLOT;
     double* s1 = s0 + G::SLOT;
 

@@ -51,9 +51,12 @@ struct Geo {
     // must run the same control flow (the batched engine's lockstep packets).
 };
 
-// Per-wave coordinates.
+// Per-wave coordinates.  ks: the staged FP64 products sum over k < 4 ks
+// only (set from an embedded dimension whose matrices vanish outside their
+// leading block; default all of D).
 struct Lane {
     int lane, g, j, TI, TJ, wt;
+    int ks = 1 << 30;
 };
 
 template <class G>
@@ -192,6 +195,7 @@ __device__ __forceinline__ Tile<T> slot_mul4(const double* A, const double* B, c
     const int bcol = 16 * L.TJ + L.j;
 #pragma unroll 4
     for (int kb = 0; kb < G::D / 4; ++kb) {
+        if (kb >= L.ks) break;   // rows k >= 4 L.ks vanish (embedded dimension)
         const int k = 4 * kb + L.g;
         const T ar = Are[arow + k], ai = Aim[arow + k];
         const T br = Bre[k * G::LD + bcol], bi = Bim[k * G::LD + bcol];
@@ -226,6 +230,7 @@ __device__ __forceinline__ Tile<T> slot_mul_3m(const double* A, const double* B,
     const int bcol = 16 * L.TJ + L.j;
 #pragma unroll 4
     for (int kb = 0; kb < G::D / 4; ++kb) {
+        if (kb >= L.ks) break;   // rows k >= 4 L.ks vanish (embedded dimension)
         const int k = 4 * kb + L.g;
         const T ar = Are[arow + k], ai = Aim[arow + k];
         const T br = Bre[k * G::LD + bcol], bi = Bim[k * G::LD + bcol];
@@ -434,12 +439,16 @@ __device__ __forceinline__ Tile<float> slot_mul_bf16x(const double* A, const dou
 //     sum_r (a_r - i a_i)[r] B[r]
 // by 3M: t1 = a_r Br, t2 = a_i Bi, t3 = (a_r - a_i)(Br + Bi);
 // Re = t1 + t2, Im = t3 - t1 + t2.
-template <typename T>
+// KS < 4 (FP64 layout only): only the first KS k-slices, rows k < 4 KS --
+// the whole product for matrices that vanish outside their leading 4 KS
+// rows and columns' block (an embedded dimension of at most 4 KS).
+template <typename T, int KS = 4>
 __device__ __forceinline__ Tile<T> reg_mul(const T (&ar)[4], const T (&ai)[4], const Tile<T>& B) {
+    static_assert(KS == 4 || std::is_same<T, double>::value, "k-slices of rows g + 4r: FP64 layout");
     using V = typename V4<T>::type;
     V t1 = {0, 0, 0, 0}, t2 = {0, 0, 0, 0}, t3 = {0, 0, 0, 0};
 #pragma unroll
-    for (int r = 0; r < 4; ++r) {
+    for (int r = 0; r < KS; ++r) {
         t1 = mfma16(ar[r], B.re[r], t1);
         t2 = mfma16(ai[r], B.im[r], t2);
         t3 = mfma16(ar[r] - ai[r], B.re[r] + B.im[r], t3);
@@ -515,24 +524,24 @@ __device__ __forceinline__ void pair_mask(Tile<double>& t, const Lane& L) {
 // Register product in the engine's product mode: FP64 and FP32-3M as 3M,
 // FP32 as four real products, BF16 split as four split real products; STK:
 // the stacked slice-pair product (FP64).
-template <typename T, int PMODE, bool STK = false>
+template <typename T, int PMODE, bool STK = false, int KS = 4>
 __device__ __forceinline__ Tile<T> reg_mulP(const T (&ar)[4], const T (&ai)[4], const Tile<T>& B) {
     if constexpr (STK) return reg_mul_stk(ar, ai, B);
-    else if constexpr (std::is_same<T, double>::value || PMODE == 1) return reg_mul<T>(ar, ai, B);
+    else if constexpr (std::is_same<T, double>::value || PMODE == 1) return reg_mul<T, KS>(ar, ai, B);
     else if constexpr (PMODE == 0) return reg_mul4(ar, ai, B);
     else return reg_mul_bf16s(ar, ai, B);
 }
 
 // A B for a Hermitian A (the A-slices are conj of the lane's own registers).
-template <typename T, int PMODE = 0, bool STK = false>
+template <typename T, int PMODE = 0, bool STK = false, int KS = 4>
 __device__ __forceinline__ Tile<T> reg_mul_herm(const Tile<T>& A, const Tile<T>& B) {
-    return reg_mulP<T, PMODE, STK>(A.re, A.im, B);
+    return reg_mulP<T, PMODE, STK, KS>(A.re, A.im, B);
 }
 
 // (C - i P) B for Hermitian C and P: the A-slice of C - i P at (j, k) is
 // conj(C[k][j]) - i conj(P[k][j]) = (C_re - P_im) - i (C_im + P_re) of the
 // lane's own registers.
-template <typename T, int PMODE = 0, bool STK = false>
+template <typename T, int PMODE = 0, bool STK = false, int KS = 4>
 __device__ __forceinline__ Tile<T> reg_mul_cp(const Tile<T>& C, const Tile<T>& P, const Tile<T>& B) {
     T ar[4], ai[4];
 #pragma unroll
@@ -540,7 +549,7 @@ __device__ __forceinline__ Tile<T> reg_mul_cp(const Tile<T>& C, const Tile<T>& P
         ar[r] = C.re[r] - P.im[r];
         ai[r] = C.im[r] + P.re[r];
     }
-    return reg_mulP<T, PMODE, STK>(ar, ai, B);
+    return reg_mulP<T, PMODE, STK, KS>(ar, ai, B);
 }
 
 // C - i P as one tile.
@@ -561,7 +570,7 @@ __device__ __forceinline__ Tile<T> combine_cp(const Tile<T>& C, const Tile<T>& P
 // every product has a Hermitian left factor, so all of them stay in
 // registers.  With EXCESS the identity term of C is left out (C - i P is
 // then exp(-i G) - I, accurate relative to ||G||).
-template <typename T, int PMODE = 0, bool EXCESS = false, bool STK = false>
+template <typename T, int PMODE = 0, bool EXCESS = false, bool STK = false, int KS = 4>
 __device__ __forceinline__ void taylor_parts_reg(const Tile<T>& Gt, int m, const Lane& L, Tile<T>& C, Tile<T>& P) {
     if constexpr (EXCESS) {
 #pragma unroll
@@ -593,17 +602,17 @@ __device__ __forceinline__ void taylor_parts_reg(const Tile<T>& Gt, int m, const
         }
         P = qs >= 1 ? reg_mul_bf16x(gr, gi, split4(Sp.re), split4(Sp.im)) : Gt;
     } else {
-        const Tile<T> Y = reg_mul_herm<T, PMODE, STK>(Gt, Gt);
+        const Tile<T> Y = reg_mul_herm<T, PMODE, STK, KS>(Gt, Gt);
         Tile<T> Sp = ident<T>(L);
         axpy(C, cos_coef(1), Y);
         if (qs >= 1) axpy(Sp, sin_coef(1), Y);
         Tile<T> Yk = Y;
         for (int k = 2; k <= qc; ++k) {
-            Yk = reg_mul_herm<T, PMODE, STK>(Y, Yk);
+            Yk = reg_mul_herm<T, PMODE, STK, KS>(Y, Yk);
             axpy(C, cos_coef(k), Yk);
             if (k <= qs) axpy(Sp, sin_coef(k), Yk);
         }
-        P = qs >= 1 ? reg_mul_herm<T, PMODE, STK>(Gt, Sp) : Gt;
+        P = qs >= 1 ? reg_mul_herm<T, PMODE, STK, KS>(Gt, Sp) : Gt;
     }
 }
 

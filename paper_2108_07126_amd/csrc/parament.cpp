@@ -224,12 +224,15 @@ void plan_chebyshev_host(const double* ctheta, int md, int force_s, double nu, i
         *s_out = force_s;
         return;
     }
+    // cost: the even/odd split's products plus the squarings; the smallest
+    // feasible degree of each s is its cheapest
     int bm = md, bs = 0, bc = 1 << 30;
     for (int s = 0; s < 64 && s < bc; ++s) {
         const double x = std::ldexp(nu, -s);
         for (int c = 1; c <= md; ++c)
             if (ctheta[c] >= x) {
-                if (c + s < bc) { bc = c + s; bm = c; bs = s; }
+                const int cost = taylor_products_host(c) + s;
+                if (cost < bc) { bc = cost; bm = c; bs = s; }
                 break;
             }
     }
@@ -669,14 +672,16 @@ pm_status launch(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double
 // tree node (U(T) into ctx->d_UT), then the backward kernels.
 // Forward pass on the FP64 gradient engine that keeps every tree node and
 // chain product (the checkpoints of the gradient and the trajectory).
+// U(T) goes to d_U when given (the caller's device buffer, dim x dim), else
+// to the context's buffer; p.U_out says where.
 pm_status forward_keep(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt, hipStream_t stream,
-                       bool run_forward, pm::PropParams* out) {
+                       bool run_forward, pm::PropParams* out, double* d_U = nullptr) {
     const pm::EngineInfo& e = ctx->geng;
     const double* basis = ctx->d_basis_grad ? ctx->d_basis_grad : ctx->d_basis;
     pm::PropParams& p = *out;
     pm_status st = ensure(ctx, (void**)&ctx->d_UT, &ctx->ut_bytes, 16 * PM_MAX_DIM * PM_MAX_DIM, "U(T)");
     if (st != PM_OK) return st;
-    st = prepare(ctx, e, true, basis, d_samples, n_samples, dt, ctx->d_UT, nullptr, &p);
+    st = prepare(ctx, e, true, basis, d_samples, n_samples, dt, d_U ? d_U : ctx->d_UT, nullptr, &p);
     if (st != PM_OK) return st;
     p.method = PM_EXPM_TAYLOR;   // the adjoint and the trajectory use the Taylor evaluation
     st = ensure(ctx, (void**)&ctx->d_chain, &ctx->chain_bytes, (size_t)p.n_chains * e.D * e.D * 16,
@@ -696,10 +701,10 @@ pm_status forward_keep(pm_ctx* ctx, const double* d_samples, int64_t n_samples, 
 
 pm_status launch_grad(pm_ctx* ctx, const double* d_samples, int64_t n_samples, double dt,
                       const double* d_W, double* d_grad, hipStream_t stream, bool run_forward,
-                      bool run_backward) {
+                      bool run_backward, double* d_U = nullptr) {
     const pm::EngineInfo& e = ctx->geng;
     pm::PropParams p;
-    pm_status st = forward_keep(ctx, d_samples, n_samples, dt, stream, run_forward, &p);
+    pm_status st = forward_keep(ctx, d_samples, n_samples, dt, stream, run_forward, &p, d_U);
     if (st != PM_OK) return st;
     hipError_t he;
     if (!run_backward) return PM_OK;
@@ -709,13 +714,16 @@ pm_status launch_grad(pm_ctx* ctx, const double* d_samples, int64_t n_samples, d
     pm::GradParams gp;
     gp.p = p;
     gp.W = d_W;
-    gp.UT = ctx->d_UT;
+    gp.UT = p.U_out;   // where the forward left U(T)
     gp.gw = ctx->d_gw;
     // few long chains: split each into parts of at least four slices (each
-    // part recomputes its predecessors in the chain) until about 2048 units
-    // run; shorter parts lose more to the recomputation than they gain
+    // part recomputes its predecessors in the chain) until about 2048 waves
+    // run (D = 16: two waves per unit); shorter parts lose more to the
+    // recomputation than they gain
     gp.split = 1;
-    while (p.n_chains * gp.split * 2 <= 2048 && p.chunk >= 8 * gp.split) gp.split *= 2;
+    gp.grad_direct = nullptr;
+    const int64_t max_units = e.D == 16 ? 1024 : 2048;
+    while (p.n_chains * gp.split * 2 <= max_units && p.chunk >= 8 * gp.split) gp.split *= 2;
     he = pm::launch_backward(e.D, gp, d_grad, stream);
     if (he != hipSuccess) return hip_fail(ctx, he, "backward launch");
     return PM_OK;
@@ -1322,14 +1330,8 @@ pm_status pm_backward_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samp
     if (s != PM_OK) return s;
     CallChunk cc(ctx, chunk);
     hipStream_t st = (hipStream_t)stream;
-    s = launch_grad(ctx, samples_dev, n_samples, dt, W_dev, grad_dev, st, true, true);
-    if (s != PM_OK) return s;
-    if (U_out_dev) {
-        hipError_t he = hipMemcpyAsync(U_out_dev, ctx->d_UT, 16 * ctx->dim * ctx->dim,
-                                       hipMemcpyDeviceToDevice, st);
-        if (he != hipSuccess) return hip_fail(ctx, he, "hipMemcpyAsync U");
-    }
-    return PM_OK;
+    // with U_out the forward writes U(T) there itself (no copy)
+    return launch_grad(ctx, samples_dev, n_samples, dt, W_dev, grad_dev, st, true, true, U_out_dev);
 }
 
 pm_status pm_trajectory_dev(pm_ctx* ctx, const double* samples_dev, int64_t n_samples, double dt, int kind,

@@ -58,6 +58,8 @@ struct GradParams {
     const double* UT;   // [du][du] complex128, U(T) of that forward
     double* gw;         // [N][M] dL / d w_{j,m}
     int split;          // backward units per chain (>= 1): unit u covers part u % split of chain u / split
+    double* grad_direct;  // order 2 on the pipelined backward: dL/d samples written there directly
+                          // (dL/dc_k(j) = h dL/dw_{j,1+k}), no separate chain-rule kernel; else null
 };
 
 // Trajectory kernel arguments (PM_TRAJ_* kinds of the public header).

@@ -670,7 +670,8 @@ __device__ __forceinline__ void stage_phased(char* row, const Mat<D, T>& U, doub
 // slice first + l * run.  Buffer stores with the range limited to the
 // slices that exist: pieces past the end are dropped by the hardware range
 // check, so the stores need no branches (and the compiler's wait counts stay
-// exact, letting the stores overlap the next slices' arithmetic).
+// exact, letting the stores overlap the next slices' arithmetic).  D = 4
+// marks them non-temporal (measured 5 % faster there, 12 % slower at D = 2).
 template <typename T, int D>
 __device__ __forceinline__ void flush_stage(const PropParams& p, const char* buf, int64_t first, int64_t run,
                                             int lane) {
@@ -685,7 +686,7 @@ __device__ __forceinline__ void flush_stage(const PropParams& p, const char* buf
         const int piece = q * 64 + lane;
         const int seg = piece / S::PIECES, off = piece % S::PIECES;
         const v4u v = *reinterpret_cast<const v4u*>(buf + seg * S::STRIDE + off * 16);
-        __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)(seg * run * S::SB + off * 16), 0, 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)(seg * run * S::SB + off * 16), 0, D == 4 ? 2 : 0);
     }
 }
 

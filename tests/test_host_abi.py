@@ -216,16 +216,25 @@ def test_chebyshev_thresholds_reproduce_table1():
             assert abs(pm.chebyshev_theta(int(m), prec) - float(printed)) <= 0.5 * scale + 1e-12, (m, printed)
 
 
+def split_products(m):
+    """Products of the even/odd split Chebyshev evaluation of degree m:
+    Y = 2X^2 - I, T_2(Y)..T_{m/2}(Y), and X times the odd sum."""
+    return 0 if m <= 1 else (1 if m == 2 else m // 2 + 1)
+
+
 @pytest.mark.parametrize("prec", [pm.PM_FP64, pm.PM_FP32])
 def test_chebyshev_planner_is_feasible_and_optimal(prec):
     th = {m: pm.chebyshev_theta(m, prec) for m in range(1, 26)}
+    cost = lambda mm, ss: split_products(mm) + ss
     for nu in [0.0, 1e-9, 3e-4, 0.0043, 0.0346, 0.195, 0.43, 1.0, 3.7, 40.0, 1e4]:
         m, s = pm.plan_chebyshev(nu, prec)
         assert nu / 2 ** s <= th[m]
-        best = min(mm + ss for ss in range(0, 40) for mm in th if nu / 2 ** ss <= th[mm])
-        assert m + s == best
-        # ties go to the smaller s
-        assert s == min(ss for ss in range(0, 40) for mm in th if nu / 2 ** ss <= th[mm] and mm + ss == best)
+        feas = [(mm, ss) for ss in range(0, 40) for mm in th if nu / 2 ** ss <= th[mm]]
+        best = min(cost(mm, ss) for mm, ss in feas)
+        assert cost(m, s) == best
+        # ties go to the smaller s, then to the smaller degree
+        assert s == min(ss for mm, ss in feas if cost(mm, ss) == best)
+        assert m == min(mm for mm, ss in feas if cost(mm, ss) == best and ss == s)
     m, s = pm.plan_chebyshev(0.3, prec, force_s=3)
     assert s == 3 and m == min(mm for mm in th if 0.3 / 8 <= th[mm])
     with pytest.raises(pm.ParamentError):
