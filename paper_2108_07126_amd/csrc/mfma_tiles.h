@@ -516,9 +516,15 @@ __device__ __forceinline__ Tile<double> reg_mul_stk(const double (&ar)[4], const
 // Zero the off-diagonal 8 x 8 blocks of a slice-pair tile (FP64 layout:
 // register r holds row g + 4r, in the second block for r >= 2).
 __device__ __forceinline__ void pair_mask(Tile<double>& t, const Lane& L) {
+    // unconditional selects: conditional stores into the tile's registers can
+    // be merged into a store through a chosen address, which keeps the tile
+    // in scratch memory
 #pragma unroll
-    for (int r = 0; r < 4; ++r)
-        if ((r >= 2) != (L.j >= 8)) t.re[r] = t.im[r] = 0.0;
+    for (int r = 0; r < 4; ++r) {
+        const bool cross = (r >= 2) != (L.j >= 8);
+        t.re[r] = cross ? 0.0 : t.re[r];
+        t.im[r] = cross ? 0.0 : t.im[r];
+    }
 }
 
 // Register product in the engine's product mode: FP64 and FP32-3M as 3M,

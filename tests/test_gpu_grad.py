@@ -50,8 +50,12 @@ def rel(a, b):
 
 
 @pytest.mark.parametrize("order", [2, 4])
-@pytest.mark.parametrize("d", [2, 3, 4, 8, 16, 17, 32, 64])
+@pytest.mark.parametrize("d", [2, 3, 4, 5, 8, 12, 16, 17, 32, 40, 64])
 def test_grad_matches_oracle(pm, d, order):
+    """Every engine class of the gradient, including embedded dimensions
+    that are not a multiple of four (the products sum over the k-slices the
+    embedded dimension reaches: d = 5 and 12 on the D = 16 pipeline, 40 on
+    D = 64)."""
     for n in (1, 5, 37):
         w = synth.random_system(d, 2, n_slices=n, h=0.11, order=order, tag=40 + n)
         V = synth.haar_unitary(np.random.default_rng(d * 7 + n), d)

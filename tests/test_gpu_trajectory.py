@@ -32,7 +32,7 @@ def _ctx(pm, w, chunk=0):
 
 
 @pytest.mark.parametrize("order", [2, 4])
-@pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 16, 20, 32, 64])
+@pytest.mark.parametrize("d", [1, 2, 3, 5, 8, 12, 16, 20, 32, 45, 64])
 def test_propagator_trajectory(pm, d, order):
     for n, chunk in ((1, 0), (77, 0), (203, 5)):
         print(f"[case] trajectory d={d} order={order} n={n} chunk={chunk}", file=sys.stderr, flush=True)
