@@ -80,12 +80,16 @@ __device__ __forceinline__ int taylor_products(int m) {
     return m / 2 + 1;
 }
 
-// Smallest s >= 0 with nu / 2^s <= th (th > 0).
+// Smallest s >= 0 with nu / 2^s <= th (th > 0).  With nu = a 2^e1 and
+// th = b 2^e2 (a, b in [1/2, 1)), log2(nu / th) lies in (e1 - e2 - 1,
+// e1 - e2 + 1), so the answer is e1 - e2 or one more; the comparisons of
+// exact power-of-two scalings decide (no division).
 __device__ __forceinline__ int min_squarings(double nu, double th) {
     if (!(nu > th)) return 0;
-    int e;
-    (void)frexp(nu / th, &e);          // nu / th in [2^(e-1), 2^e), up to rounding
-    int s = e;
+    int e1, e2;
+    (void)frexp(nu, &e1);
+    (void)frexp(th, &e2);
+    int s = e1 - e2;
     if (ldexp(nu, -s) > th) s += 1;
     else if (s > 0 && ldexp(nu, -(s - 1)) <= th) s -= 1;
     return s;
@@ -357,11 +361,12 @@ __device__ __forceinline__ double rows_max(double x) {
 }
 
 // Single-precision variants for row sums of entry bounds: the sum of 16
-// non-negative terms in FP32 is within 16 * 2^-24 of exact, the square roots
-// within 2^-22; rows_max_f inflates the result by 2^-16 so it stays an upper
-// bound, and returns it in FP64.
+// non-negative terms in FP32 is within 16 * 2^-24 of exact, the hardware
+// square root (no correctly rounded expansion: one instruction) within
+// 2^-22; rows_max_f inflates the result by 2^-16 so it stays an upper bound,
+// and returns it in FP64.
 __device__ __forceinline__ float abs_bound_f(double re, double im) {
-    return __builtin_sqrtf((float)(re * re + im * im));
+    return __builtin_amdgcn_sqrtf((float)(re * re + im * im));
 }
 
 __device__ __forceinline__ float row16_sum_f(float x) {
@@ -380,11 +385,12 @@ __device__ __forceinline__ double rows_max_f(float x) {
     return (double)fmaxf(fmaxf(a, b), fmaxf(c, d)) * (1.0 + 0x1p-16) + 0x1p-60;
 }
 
-// Upper bound of |re + i im| from a single-precision square root, inflated
-// past its rounding (relative error < 2^-22) so the bound never falls short.
+// Upper bound of |re + i im| from the hardware single-precision square root,
+// inflated past its rounding (relative error < 2^-22) so the bound never
+// falls short.
 __device__ __forceinline__ double abs_bound(double re, double im) {
     const float q = (float)(re * re + im * im);
-    return (double)__builtin_sqrtf(q) * (1.0 + 0x1p-20) + 0x1p-60;
+    return (double)__builtin_amdgcn_sqrtf(q) * (1.0 + 0x1p-20) + 0x1p-60;
 }
 
 }  // namespace pm
