@@ -468,15 +468,18 @@ backward_mfma(GradParams gp) {
 // multiplies the block's earlier chains and forms Z = W^H U(T).  Same
 // products as backward_mfma; the block's waves meet at two barriers per
 // slice, all the same number of times (units past the end idle through them).
-template <int NT, bool BL, int KS>
-__global__ void __launch_bounds__(64 * NT) __attribute__((amdgpu_waves_per_eu(2, 8)))
+// A block holds UPB units: waves 0 .. UPB-1 take role 0 of units 0 .. UPB-1
+// and waves UPB .. 2 UPB-1 role 1.  A CU places a block's waves on its four
+// SIMDs in turn, so with UPB = 4 every SIMD runs one wave of each role (the
+// lighter recursion beside the heavier derivative) instead of two of one.
+template <int NT, bool BL, int KS, int UPB>
+__global__ void __launch_bounds__(128 * UPB) __attribute__((amdgpu_waves_per_eu(2, 8)))
 backward_pipe(GradParams gp) {
     using G = Geo<16, NT>;   // G::NT: chains per leaf of the forward's tree
-    static_assert(NT % 2 == 0, "two waves per unit");
     const PropParams& p = gp.p;
     extern __shared__ double dsm[];
     double* slots = dsm;
-    double* red = slots + NT * 2 * G::SLOT;
+    double* red = slots + 2 * UPB * 2 * G::SLOT;
     double* lbasis = red + G::TD * 16 + 2;
     double* hand = lbasis + (BL ? p.M * 512 : 0);    // per unit: 2 tiles of 512 doubles, then m, s
 
@@ -488,7 +491,8 @@ backward_pipe(GradParams gp) {
     L.TI = L.TJ = 0;
     L.ks = (p.du + 3) / 4;   // the tiles vanish outside the leading du x du block
     const int wave = wave_uniform((int)(threadIdx.x >> 6));
-    const int role = wave & 1;
+    const int role = wave / UPB;
+    const int ub = wave % UPB;   // the unit within the block
     double* s0 = slots + wave * 2 * G::SLOT;
     double* s1 = s0 + G::SLOT;
     if constexpr (BL) {
@@ -497,7 +501,7 @@ backward_pipe(GradParams gp) {
     }
     __syncthreads();
     const double* bas = BL ? lbasis : p.basis;
-    double* hb = hand + (wave >> 1) * 1040;
+    double* hb = hand + ub * 1040;
     int* hms = reinterpret_cast<int*>(hb + 1024);
     // lane-private handoff layout: tile t, register r of lane l at t * 512 + r * 64 + l (re), + 256 (im)
     auto put = [&](int t, const Tile<double>& x) {
@@ -517,7 +521,7 @@ backward_pipe(GradParams gp) {
         return x;
     };
 
-    const int64_t unit = (int64_t)blockIdx.x * (NT / 2) + (wave >> 1);
+    const int64_t unit = (int64_t)blockIdx.x * UPB + ub;
     const int64_t chain = unit / gp.split;
     const int64_t part = unit % gp.split;
     const bool live = chain < p.n_chains;
@@ -897,28 +901,45 @@ hipError_t launch_bwd(const GradParams& gp, size_t lds, hipStream_t stream) {
     return hipGetLastError();
 }
 
+// LDS of backward_pipe with UPB units per block: two staging slots per wave,
+// the reduction row, the basis when BL, and a handoff area per unit.
+constexpr size_t kPipeUPB = 4;
+size_t pipe_lds_bytes(int M, bool bl) {
+    using G = Geo<16, 4>;
+    return sizeof(double) * (2 * kPipeUPB * 2 * G::SLOT + G::TD * 16 + 2 + (bl ? (size_t)M * 512 : 0) +
+                             kPipeUPB * 1040);
+}
+
 // KS: register products over the k-slices that the embedded dimension
 // reaches (1 for du <= 4, 2 for du <= 8, else all 4).
 template <bool BL, int KS>
-hipError_t launch_bwd_pipe(const GradParams& gp, size_t lds, hipStream_t stream) {
-    constexpr int NT = 4;   // two units of two waves per block
+hipError_t launch_bwd_pipe(const GradParams& gp, hipStream_t stream) {
+    constexpr int NT = 4;   // the forward's chains per leaf
+    constexpr int UPB = (int)kPipeUPB;
     static bool attr_set = false;
     if (!attr_set) {
-        hipError_t e = hipFuncSetAttribute((const void*)backward_pipe<NT, BL, KS>,
+        hipError_t e = hipFuncSetAttribute((const void*)backward_pipe<NT, BL, KS, UPB>,
                                            hipFuncAttributeMaxDynamicSharedMemorySize, 160 * 1024);
         if (e != hipSuccess) return e;
         attr_set = true;
     }
     const int64_t units = gp.p.n_chains * gp.split;
-    const int64_t blocks = (units + NT / 2 - 1) / (NT / 2);
-    hipLaunchKernelGGL((backward_pipe<NT, BL, KS>), dim3((unsigned)blocks), dim3(64 * NT), lds, stream, gp);
+    const int64_t blocks = (units + UPB - 1) / UPB;
+    hipLaunchKernelGGL((backward_pipe<NT, BL, KS, UPB>), dim3((unsigned)blocks), dim3(128 * UPB),
+                       pipe_lds_bytes(gp.p.M, BL), stream, gp);
     return hipGetLastError();
 }
 
-template <bool BL>
-hipError_t launch_bwd_pipe_ks(const GradParams& gp, size_t lds, hipStream_t stream) {
-    if (gp.p.du <= 4) return launch_bwd_pipe<BL, 1>(gp, lds, stream);
-    return gp.p.du <= 8 ? launch_bwd_pipe<BL, 2>(gp, lds, stream) : launch_bwd_pipe<BL, 4>(gp, lds, stream);
+// The basis stays in LDS only while the block's LDS fits in 160 KiB.
+template <int KS>
+hipError_t launch_bwd_pipe_bl(const GradParams& gp, hipStream_t stream) {
+    const bool bl = gp.p.basis_lds != 0 && pipe_lds_bytes(gp.p.M, true) <= 160 * 1024;
+    return bl ? launch_bwd_pipe<true, KS>(gp, stream) : launch_bwd_pipe<false, KS>(gp, stream);
+}
+
+hipError_t launch_bwd_pipe_ks(const GradParams& gp, hipStream_t stream) {
+    if (gp.p.du <= 4) return launch_bwd_pipe_bl<1>(gp, stream);
+    return gp.p.du <= 8 ? launch_bwd_pipe_bl<2>(gp, stream) : launch_bwd_pipe_bl<4>(gp, stream);
 }
 
 template <int D, int NT, bool BL>
@@ -961,13 +982,12 @@ hipError_t launch_backward(int D, const GradParams& gp, double* grad_samples, hi
     const bool bl = gp.p.basis_lds != 0;
     if (bl) lds += sizeof(double) * (size_t)gp.p.M * TD * TD * 512;
     hipError_t e;
-    // D = 16: the two-wave pipeline, with a handoff area of 1040 doubles per
-    // unit; at order 2 it also writes dL/d samples itself
-    const size_t lds_pipe = lds + sizeof(double) * 1040 * 2;
+    // D = 16: the two-wave pipeline; at order 2 it also writes dL/d samples
+    // itself
     GradParams gq = gp;
     gq.grad_direct = (D == 16 && gp.p.order == 2) ? grad_samples : nullptr;
     switch (D) {
-        case 16: e = bl ? launch_bwd_pipe_ks<true>(gq, lds_pipe, stream) : launch_bwd_pipe_ks<false>(gq, lds_pipe, stream); break;
+        case 16: e = launch_bwd_pipe_ks(gq, stream); break;
         case 32: e = launch_bwd<32, 1, false>(gp, lds, stream); break;
         case 64: e = launch_bwd<64, 1, false>(gp, lds, stream); break;
         default: return hipErrorInvalidValue;

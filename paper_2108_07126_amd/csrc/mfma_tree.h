@@ -127,15 +127,53 @@ __device__ void tree_reduce_groups(const PropParams& p, int64_t leaf, Tile<doubl
     store_root<G>(p, Q, L);
 }
 
+// A node published to the other XCDs inside one launch, written and read as
+// agent-scope atomic accesses.  Those bypass the per-XCD L2s' private state
+// (the stores write through to the device's coherence point and the loads
+// read from it), so a node is visible to every XCD once its stores have
+// completed: the publisher waits for that completion before it takes the
+// ticket, and the ticket's last taker reads the nodes after the ticket.  A
+// release/acquire fence pair would add an L2 writeback and an invalidate
+// (for ordinary cached stores and loads) per node, which none of these
+// accesses needs.
+template <class G>
+__device__ __forceinline__ void node_store_coherent(double* node, const Tile<double>& t, const Lane& L) {
+    const int col = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        __hip_atomic_store(&node[(row * G::D + col) * 2 + 0], t.re[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        __hip_atomic_store(&node[(row * G::D + col) * 2 + 1], t.im[r], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    // the stores complete before anything after this point is issued (and
+    // the compiler keeps them before it)
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+    __builtin_amdgcn_s_waitcnt(0);
+    __atomic_signal_fence(__ATOMIC_SEQ_CST);
+}
+
+template <class G>
+__device__ __forceinline__ Tile<double> node_load_coherent(double* node, const Lane& L) {
+    Tile<double> t;
+    const int col = 16 * L.TJ + L.j;
+#pragma unroll
+    for (int r = 0; r < 4; ++r) {
+        const int row = 16 * L.TI + crow<double>(L.g, r);
+        t.re[r] = __hip_atomic_load(&node[(row * G::D + col) * 2 + 0], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+        t.im[r] = __hip_atomic_load(&node[(row * G::D + col) * 2 + 1], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    }
+    return t;
+}
+
 // The same tree for a block of NT one-wave teams (16-wide tiles) that all
-// stay into it: team 0 publishes the block's node and takes the group's
-// ticket, and the outcome goes to every team through LDS.  When the block is
-// its group's last arrival, team 0 loads the group's nodes together and
-// stages node q in LDS slot q; the group's product is then formed pairwise,
-// slot q + w times slot q into slot q for w = 1, 2, 4 (later nodes on the
-// left), four products at once in the first round: three dependent products
-// per level instead of seven.  Same nodes and root as tree_reduce_groups up
-// to the association inside each group.
+// stay into it: team 0 publishes the block's node (coherent stores, above)
+// and takes the group's ticket, and the outcome goes to every team through
+// LDS.  When the block is its group's last arrival, team 0 loads the group's
+// nodes together and stages node q in LDS slot q; the group's product is
+// then formed pairwise, slot q + w times slot q into slot q for w = 1, 2, 4
+// (later nodes on the left), four products at once in the first round:
+// three dependent products per level instead of seven.  Same nodes and root
+// as tree_reduce_groups up to the association inside each group.
 template <class G, int NT>
 __device__ void tree_reduce_teams(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L, int team,
                                   double* slots, int* tick) {
@@ -150,15 +188,11 @@ __device__ void tree_reduce_teams(const PropParams& p, int64_t leaf, Tile<double
             if (p.store_nodes && team == 0) node_store<G>(p.nodes + (off + idx) * NN, Q, L);
         } else {
             if (team == 0) {
-                node_store<G>(p.nodes + (off + idx) * NN, Q, L);
-                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "agent");
+                node_store_coherent<G>(p.nodes + (off + idx) * NN, Q, L);
                 unsigned v = 0;
                 if (L.lane == 0) v = atomicAdd(&p.counters[poff + grp], 1u);
                 const unsigned t = (unsigned)__builtin_amdgcn_readfirstlane((int)__shfl(v, 0));
-                if (t == (unsigned)(members - 1)) {
-                    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "agent");
-                    if (L.lane == 0) atomicExch(&p.counters[poff + grp], 0u);
-                }
+                if (t == (unsigned)(members - 1) && L.lane == 0) atomicExch(&p.counters[poff + grp], 0u);
                 if (L.lane == 0) *tick = (int)t;
             }
             __syncthreads();
@@ -174,7 +208,7 @@ __device__ void tree_reduce_teams(const PropParams& p, int64_t leaf, Tile<double
 #pragma unroll
                     for (int q = 0; q < kFanIn / 2; ++q)
                         X[q] = (h + q < members && first + h + q != idx)
-                                   ? node_load<G>(p.nodes + (off + first + h + q) * NN, L)
+                                   ? node_load_coherent<G>(p.nodes + (off + first + h + q) * NN, L)
                                    : Q;
 #pragma unroll
                     for (int q = 0; q < kFanIn / 2; ++q)
