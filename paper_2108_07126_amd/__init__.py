@@ -72,6 +72,7 @@ SIGNATURES = {
     "pm_tuning_set": (ctypes.c_int, [ctypes.c_char_p, ctypes.c_int, ctypes.c_int, ctypes.c_int64]),
     "pm_set_expm_policy": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int, ctypes.c_int]),
     "pm_set_chunk": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int64]),
+    "pm_set_chain_skew": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pm_set_expm_method": (ctypes.c_int, [ctypes.c_void_p, ctypes.c_int]),
     "pm_chebyshev_theta": (ctypes.c_int, [ctypes.c_int, ctypes.c_int, _c_double_p]),
     "pm_plan_chebyshev": (ctypes.c_int, [ctypes.c_double, ctypes.c_int, ctypes.c_int, ctypes.c_int, _c_int_p,
@@ -292,6 +293,10 @@ class Context:
 
     def set_chunk(self, chunk: int = 0):
         _check(_lib.pm_set_chunk(self._h, chunk), self._h)
+
+    def set_chain_skew(self, percent: int = -1):
+        """Percent longer chains for the first-dispatched blocks (-1 automatic, 0 equal chains)."""
+        _check(_lib.pm_set_chain_skew(self._h, percent), self._h)
 
     def set_expm_method(self, method: int = PM_EXPM_TAYLOR):
         """PM_EXPM_TAYLOR (default) or PM_EXPM_CHEBYSHEV (the paper's series)."""

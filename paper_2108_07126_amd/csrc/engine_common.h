@@ -23,6 +23,12 @@ __device__ __forceinline__ double sin_coef(int k) {
     return t[k];
 }
 
+// First slice of chain c: the first p.n_long chains hold p.chunk_long slices
+// each, the rest p.chunk (for c = n_chains, at least N).
+__device__ __forceinline__ int64_t chain_first(const PropParams& p, int64_t c) {
+    return c <= p.n_long ? c * p.chunk_long : p.n_long * p.chunk_long + (c - p.n_long) * p.chunk;
+}
+
 // Wave-uniform copy of a value that every lane already holds.
 __device__ __forceinline__ double wave_uniform(double x) {
     const long long b = __double_as_longlong(x);

@@ -91,8 +91,8 @@ propagate_mfma(PropParams p) {
 
     // this team's chain of consecutive slices (empty past the end)
     const int64_t chain = (int64_t)blockIdx.x * NT + team;
-    const int64_t j0 = min(p.n_slices, chain * p.chunk);
-    const int64_t j1 = min(p.n_slices, j0 + p.chunk);
+    const int64_t j0 = min(p.n_slices, chain_first(p, chain));
+    const int64_t j1 = min(p.n_slices, chain_first(p, chain + 1));
     static_assert(!PAIR || D == 16, "slice pairs live in the 16-wide tile");
     static_assert(!M6 || (std::is_same<T, double>::value && !PAIR), "sixth order: FP64, one slice per tile");
     // PAIR: halves [j0, jm) and [jm, j1); otherwise one run [j0, j1)

@@ -45,6 +45,8 @@ struct pm_ctx {
     int max_degree = PM_MAX_TAYLOR_DEGREE;
     int force_s = -1;
     int64_t chunk_override = 0;
+    int chain_skew = -1;         // pm_set_chain_skew: percent, -1 automatic
+    int n_cu = 256;              // compute units of the device
     int64_t call_chunk = 0;      // chain length planned for the current call (0: none)
     int64_t ws_limit = 0;        // device workspace limit in bytes (0: none)
     int method = PM_EXPM_TAYLOR;
@@ -437,13 +439,12 @@ int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool keep_
         target = g_tune_chains[tc][precision];
     int64_t c = (N + target - 1) / target;
     if (c < 1) c = 1;
-    // Short MFMA chains: below eight slices (four for the gradient's and the
-    // trajectory's forward pass, whose backward or replay has more work per
-    // slice) the product tree's per-leaf publication (an agent-scope release
-    // and acquire per node) costs more than the parallelism gains.  Measured
-    // on the d=16 workload: N = 8192, chains of 8 beat 4 by 16 %; N = 4096
-    // gradient, chains of 4 beat 2 by 13 % and 8 by 30 %.
-    const int64_t cmin = keep_nodes ? 4 : 8;
+    // Short MFMA chains: below four slices the product tree's extra leaves
+    // cost more than the parallelism gains.  Measured on the d=16 workload
+    // (graph replay): N = 8192, chains of 4 (512 blocks, uneven chains) 52.7
+    // us, of 8 53.9 us, of 2 75.1 us; N = 4096 gradient, chains of 4 beat 2
+    // by 13 % and 8 by 30 %.
+    const int64_t cmin = 4;
     if (e.kind == pm::ENGINE_MFMA && c < cmin) c = cmin;
     const int64_t u = e.chunk_unit;
     return ((c + u - 1) / u) * u;
@@ -462,6 +463,34 @@ int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, b
     // CF4: a chain starts at a slice boundary (an even exponential index)
     if (ctx->order == PM_ORDER_CF4 && (c & 1)) ++c;
     return c;
+}
+
+// Uneven chains for a D = 16 launch of exactly two blocks per CU.  A CU
+// places the two blocks' waves two to a SIMD, and the SIMD's issue favours
+// the older wave: the blocks dispatched first (one per CU, the lower block
+// indices) finish their chains well before the second ones, which then run
+// their last slices one wave per SIMD, too few to keep the MFMA pipe busy.
+// Giving the first-dispatched blocks' chains `pct` percent more slices (the
+// others correspondingly fewer) lets both finish together.  Measured on the
+// d = 16 workload (graph replay, one box): N = 2^17 FP64 334 -> 321 us at 20 %
+// and 317 us at 25 %; FP32-3M 249 -> 234 us at 20 %; N = 32768 FP64 117 ->
+// 111 us at 25 %.  The product over the chains is unchanged (the tree still
+// multiplies consecutive chains in order); only its association differs.
+void skew_chains(const pm_ctx* ctx, const pm::EngineInfo& e, pm::PropParams& p) {
+    if (e.kind != pm::ENGINE_MFMA || e.D != 16) return;
+    const int pct = ctx->chain_skew >= 0 ? ctx->chain_skew : (ctx->precision == PM_FP64 ? 25 : 20);
+    if (pct <= 0 || p.n_leaves != 2 * (int64_t)ctx->n_cu) return;
+    const bool even = ctx->order == PM_ORDER_CF4;   // chains start at a slice boundary
+    const int64_t n_long = (int64_t)ctx->n_cu * e.chains_per_leaf;
+    int64_t cl = p.chunk + (p.chunk * pct + 50) / 100;
+    if (even && (cl & 1)) ++cl;
+    const int64_t rest = p.n_slices - n_long * cl, n_short = p.n_chains - n_long;
+    if (cl <= p.chunk || n_short <= 0 || rest < n_short) return;
+    int64_t cs = (rest + n_short - 1) / n_short;
+    if (even && (cs & 1)) ++cs;
+    p.n_long = n_long;
+    p.chunk_long = cl;
+    p.chunk = cs;
 }
 
 // ---- device workspace under the context's limit (pm_set_workspace_limit)
@@ -617,8 +646,11 @@ pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, bool keep_nodes, const d
     p.n_samples = n_samples;
     p.n_slices = N;
     p.chunk = chunk;
+    p.chunk_long = chunk;
+    p.n_long = 0;
     p.n_chains = chains;
     p.n_leaves = leaves;
+    if (!keep_nodes) skew_chains(ctx, e, p);
     p.slices_out = d_slices;
     p.nodes = nodes;
     p.counters = tickets;
@@ -941,6 +973,9 @@ pm_status pm_create(pm_ctx** out, int device, int precision) {
     if (!ctx) return PM_E_OOM;
     ctx->device = device;
     ctx->precision = precision;
+    int cus = 0;
+    if (hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, device) == hipSuccess && cus > 0)
+        ctx->n_cu = cus;
     *out = ctx;
     return PM_OK;
 }
@@ -977,6 +1012,13 @@ pm_status pm_set_expm_policy(pm_ctx* ctx, int max_taylor_degree, int force_s) {
         return fail(ctx, PM_E_INVALID_ARG, "max_taylor_degree in [1, 21], force_s in [-1, 62]");
     ctx->max_degree = max_taylor_degree;
     ctx->force_s = force_s;
+    return PM_OK;
+}
+
+pm_status pm_set_chain_skew(pm_ctx* ctx, int percent) {
+    if (!ctx || percent < -1 || percent > 100)
+        return ctx ? fail(ctx, PM_E_INVALID_ARG, "chain skew must be -1 (automatic) or 0..100") : PM_E_INVALID_ARG;
+    ctx->chain_skew = percent;
     return PM_OK;
 }
 

@@ -29,8 +29,10 @@ struct PropParams {
     const double* samples;    // [K][n_samples]
     int64_t n_samples;
     int64_t n_slices;         // N
-    int64_t chunk;            // consecutive slices per chain
-    int64_t n_chains;         // ceil(N / chunk)
+    int64_t chunk;            // consecutive slices per chain (after the first n_long chains)
+    int64_t n_long;           // the first n_long chains hold chunk_long slices each (0: none)
+    int64_t chunk_long;
+    int64_t n_chains;         // chains covering the N slices
     int64_t n_leaves;         // leaves of the product tree (blocks or waves)
     void* slices_out;         // nullptr or [N][du][du] complex (c128 / c64)
     double* nodes;            // tree nodes, [2 * n_leaves][D][D] complex128

@@ -273,3 +273,50 @@ def test_small_dims_shift_and_degenerate_spectra(pm, d, case):
     e32 = orc.relative_frobenius(U32v, Uo)
     say(f"  fp32 s={s32} rel err {e32:.3e} (bound {tol32(301, d, s32):.3e})")
     assert e32 <= tol32(301, d, s32)
+
+
+@pytest.mark.parametrize("case", ["fp64_order4", "fp32_3m_order2", "fp64_cf4", "fp64_pairs_d8"])
+def test_uneven_chains(pm, case):
+    """A 16-wide-tile launch of exactly two blocks of four chains per compute
+    unit gives the first-dispatched blocks' chains more slices
+    (pm_set_chain_skew).  Equal chains, the automatic skew and 60 % all
+    exponentiate every slice once (per-slice output identical), give the same
+    U(T) to rounding, and match the oracle."""
+    import torch
+    n_cu = torch.cuda.get_device_properties(0).multi_processor_count
+    chains, chunk = 2 * n_cu * 4, 6
+    prec = FP32_3M if case == "fp32_3m_order2" else 0
+    d = 8 if case == "fp64_pairs_d8" else 16
+    order = {"fp64_order4": 4, "fp32_3m_order2": 2, "fp64_cf4": orc.CF4, "fp64_pairs_d8": 2}[case]
+    n = chains * chunk // (2 if order == orc.CF4 else 1)   # CF4: two exponentials per slice
+    w = synth.random_system(d, 3, n_slices=n, h=0.02, order=order, tag=77)
+    slices = order != orc.CF4
+    out = {}
+    for skew in (0, -1, 60):
+        say(f"[case] uneven chains {case} d={d} N={n} chunk={chunk} skew={skew}")
+        with pm.Context(0, prec) as ctx:
+            ctx.set_hamiltonian(w.H0, w.Hk, order)
+            ctx.set_chunk(chunk)
+            ctx.set_chain_skew(skew)
+            assert ctx.launch_shape(w.n_samples)[1:] == (chains, chains // 4)
+            out[skew] = ctx.equiprop(w.samples, w.h, return_slices=slices)
+    ref = out[0]
+    if slices:
+        Uo, slo = orc.propagate(w.H0, w.Hk, w.samples, w.h, order, return_slices=True)
+    else:
+        Uo = orc.propagate(w.H0, w.Hk, w.samples, w.h, order)
+    for skew, res in out.items():
+        U, sl = res if slices else (res, None)
+        if prec == 0:
+            assert orc.relative_frobenius(U, Uo) <= TOL64, skew
+            assert orc.relative_frobenius(U, ref[0] if slices else ref) <= 1e-13, skew
+        else:
+            assert orc.relative_frobenius(U, Uo) <= tol(FP32_3M, n, d), skew
+        if slices:
+            # a slice's exponential does not depend on its chain (slice pairs:
+            # the tile's plan covers both slices of a pair, so rounding may differ)
+            if case == "fp64_pairs_d8":
+                assert np.max(np.abs(sl - ref[1])) <= 1e-14, skew
+            else:
+                assert np.array_equal(sl, ref[1]), skew
+            assert np.max(np.abs(sl - slo)) <= (1e-13 if prec == 0 else tol_slice(FP32_3M, d)), skew
