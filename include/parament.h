@@ -324,16 +324,18 @@ pm_status pm_set_expm_policy(pm_ctx *ctx, int max_taylor_degree, int force_s);
 pm_status pm_set_chunk(pm_ctx *ctx, int64_t chunk);
 
 /* Uneven chain lengths (the Reduction section's chains need not be equal;
- * only their order matters).  When a 16-wide-tile propagation (dimension
- * 5..16, or two slices of dimension <= 8 per tile) runs exactly two blocks
- * of chains per compute unit, the chains of the blocks each unit receives
- * first take `percent` percent more slices and the others correspondingly
- * fewer: the first-dispatched waves win the SIMD's issue arbitration and
- * would otherwise finish early, leaving the second ones to run alone.
- * percent in [0, 100] (0: equal chains), -1 (default) the automatic choice:
- * 25 in PM_FP64, 20 otherwise.  U(T) changes only by the association of the
- * chain products (rounding).  Not applied to the gradient's or the
- * trajectory's forward pass.  PM_E_INVALID_ARG outside that range. */
+ * only their order matters).  When a propagation of dimension <= 16 runs
+ * exactly two blocks of chains per compute unit, the chains of the blocks
+ * each unit receives first take `percent` percent more slices and the others
+ * correspondingly fewer: the first-dispatched waves win the SIMD's issue
+ * arbitration and would otherwise finish early, leaving the second ones to
+ * run alone.  percent in [0, 100] (0: equal chains), -1 (default) the
+ * automatic choice: 25 in PM_FP64; in the other precisions 20 for dimensions
+ * 5..16 (and slice pairs of dimension <= 8), 0 for dimensions <= 4.  Chains
+ * of dimensions <= 4 stay whole multiples of 1024 slices.  U(T) changes only
+ * by the association of the chain products (rounding).  Not applied to the
+ * gradient's or the trajectory's forward pass.  PM_E_INVALID_ARG outside
+ * that range. */
 pm_status pm_set_chain_skew(pm_ctx *ctx, int percent);
 
 /* ---- device workspace ---------------------------------------------------

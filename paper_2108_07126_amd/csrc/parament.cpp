@@ -476,18 +476,28 @@ int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, b
 // and 317 us at 25 %; FP32-3M 249 -> 234 us at 20 %; N = 32768 FP64 117 ->
 // 111 us at 25 %.  The product over the chains is unchanged (the tree still
 // multiplies consecutive chains in order); only its association differs.
+// The small-dimension engine's blocks of four one-chain waves meet the same
+// arbitration at two blocks per CU; its chains stay in whole units (and at
+// most 2^20 slices).  Measured there (d = 2, N = 2^26, FP64): 567 -> 546 us
+// without and 1251 -> 1188 us with per-slice output at 25 %; in FP32 20 %
+// gained nothing and 40 % lost 12 %, so its reduced modes keep equal chains.
 void skew_chains(const pm_ctx* ctx, const pm::EngineInfo& e, pm::PropParams& p) {
-    if (e.kind != pm::ENGINE_MFMA || e.D != 16) return;
-    const int pct = ctx->chain_skew >= 0 ? ctx->chain_skew : (ctx->precision == PM_FP64 ? 25 : 20);
+    const bool valu = e.kind == pm::ENGINE_VALU;
+    if (!valu && !(e.kind == pm::ENGINE_MFMA && e.D == 16)) return;
+    const int pct = ctx->chain_skew >= 0 ? ctx->chain_skew : (ctx->precision == PM_FP64 ? 25 : (valu ? 0 : 20));
     if (pct <= 0 || p.n_leaves != 2 * (int64_t)ctx->n_cu) return;
     const bool even = ctx->order == PM_ORDER_CF4;   // chains start at a slice boundary
+    const int64_t u = e.chunk_unit;
+    auto whole = [&](int64_t c) {
+        c = (c + u - 1) / u * u;
+        return even && (c & 1) ? c + 1 : c;
+    };
     const int64_t n_long = (int64_t)ctx->n_cu * e.chains_per_leaf;
-    int64_t cl = p.chunk + (p.chunk * pct + 50) / 100;
-    if (even && (cl & 1)) ++cl;
+    const int64_t cl = whole(p.chunk + (p.chunk * pct + 50) / 100);
     const int64_t rest = p.n_slices - n_long * cl, n_short = p.n_chains - n_long;
-    if (cl <= p.chunk || n_short <= 0 || rest < n_short) return;
-    int64_t cs = (rest + n_short - 1) / n_short;
-    if (even && (cs & 1)) ++cs;
+    if (cl <= p.chunk || n_short <= 0 || rest < n_short || (valu && cl > (int64_t(1) << 20))) return;
+    const int64_t cs = whole((rest + n_short - 1) / n_short);
+    if (cs >= p.chunk) return;
     p.n_long = n_long;
     p.chunk_long = cl;
     p.chunk = cs;

@@ -737,8 +737,9 @@ propagate_valu(PropParams p) {
     char* sbuf = stage_lds + wib * S::BUF;
     char* srow = sbuf + lane * S::STRIDE;
     // a lane's run is a multiple of 16 slices (two sample blocks, 2 S::R)
-    const int64_t run = wave < p.n_chains ? p.chunk / 64 : 0;
-    const int64_t base = wave * p.chunk + (int64_t)lane * run;
+    const int64_t cfirst = chain_first(p, wave);
+    const int64_t run = wave < p.n_chains ? (chain_first(p, wave + 1) - cfirst) / 64 : 0;
+    const int64_t base = cfirst + (int64_t)lane * run;
     const double lth = lane_theta_of(p, lane);
     const double lcth = lane_ctheta_of(p, lane);
     constexpr bool kF64 = std::is_same<T, double>::value;
@@ -815,7 +816,7 @@ propagate_valu(PropParams p) {
     auto flush = [&](int64_t i1) {
         if constexpr (OUT == OUT_STAGED) {
             wave_lds_sync();
-            flush_stage<T, D>(p, sbuf, wave * p.chunk + i1 - S::R, run, lane);
+            flush_stage<T, D>(p, sbuf, cfirst + i1 - S::R, run, lane);
             wave_lds_sync();
         }
     };
