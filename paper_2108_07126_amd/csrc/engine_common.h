@@ -29,6 +29,24 @@ __device__ __forceinline__ int64_t chain_first(const PropParams& p, int64_t c) {
     return c <= p.n_long ? c * p.chunk_long : p.n_long * p.chunk_long + (c - p.n_long) * p.chunk;
 }
 
+// The block copies n doubles (n even, both ends 16-byte aligned) from global
+// memory into LDS in 16-byte pieces, eight loads in flight per thread before
+// their stores.  The caller synchronises the block afterwards.
+__device__ __forceinline__ void block_copy_to_lds(double* dst, const double* src, int n) {
+    const int n2 = n / 2, step = (int)blockDim.x;
+    const double2* s2 = reinterpret_cast<const double2*>(src);
+    double2* d2 = reinterpret_cast<double2*>(dst);
+    int i = (int)threadIdx.x;
+    for (; i + 7 * step < n2; i += 8 * step) {
+        double2 v[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) v[q] = s2[i + q * step];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) d2[i + q * step] = v[q];
+    }
+    for (; i < n2; i += step) d2[i] = s2[i];
+}
+
 // Wave-uniform copy of a value that every lane already holds.
 __device__ __forceinline__ double wave_uniform(double x) {
     const long long b = __double_as_longlong(x);

@@ -350,7 +350,7 @@ backward_mfma(GradParams gp) {
     double* s1 = s0 + G::SLOT;
     if constexpr (BL) {
         const int n = p.M * G::TW * 512;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
+        block_copy_to_lds(lbasis, p.basis, n);
         __syncthreads();
     }
     const double* bas = BL ? lbasis : p.basis;
@@ -497,7 +497,7 @@ backward_pipe(GradParams gp) {
     double* s1 = s0 + G::SLOT;
     if constexpr (BL) {
         const int n = p.M * 512;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
+        block_copy_to_lds(lbasis, p.basis, n);
     }
     __syncthreads();
     const double* bas = BL ? lbasis : p.basis;
@@ -751,7 +751,7 @@ trajectory_mfma(TrajParams tp) {
     double* s1 = s0 + G::SLOT;
     if constexpr (BL) {
         const int n = p.M * G::TW * 512;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
+        block_copy_to_lds(lbasis, p.basis, n);
         __syncthreads();
     }
     const double* bas = BL ? lbasis : p.basis;

@@ -84,7 +84,7 @@ propagate_mfma(PropParams p) {
     // the block's copy of the basis (same for every slice)
     if constexpr (BL) {
         const int n = p.M * G::TW * 512;
-        for (int i = threadIdx.x; i < n; i += blockDim.x) lbasis[i] = p.basis[i];
+        block_copy_to_lds(lbasis, p.basis, n);
         __syncthreads();
     }
     const double* bas = BL ? lbasis : p.basis;

@@ -168,12 +168,13 @@ __device__ __forceinline__ Tile<double> node_load_coherent(double* node, const L
 // The same tree for a block of NT one-wave teams (16-wide tiles) that all
 // stay into it: team 0 publishes the block's node (coherent stores, above)
 // and takes the group's ticket, and the outcome goes to every team through
-// LDS.  When the block is its group's last arrival, team 0 loads the group's
-// nodes together and stages node q in LDS slot q; the group's product is
-// then formed pairwise, slot q + w times slot q into slot q for w = 1, 2, 4
-// (later nodes on the left), four products at once in the first round:
-// three dependent products per level instead of seven.  Same nodes and root
-// as tree_reduce_groups up to the association inside each group.
+// LDS.  When the block is its group's last arrival, the teams load the
+// group's nodes (two each, all at once) and stage node q in LDS slot q; the
+// group's product is then formed pairwise, slot q + w times slot q into slot
+// q for w = 1, 2, 4 (later nodes on the left), four products at once in the
+// first round: three dependent products per level instead of seven.  Same
+// nodes and root as tree_reduce_groups up to the association inside each
+// group.
 template <class G, int NT>
 __device__ void tree_reduce_teams(const PropParams& p, int64_t leaf, Tile<double> Q, const Lane& L, int team,
                                   double* slots, int* tick) {
@@ -199,21 +200,20 @@ __device__ void tree_reduce_teams(const PropParams& p, int64_t leaf, Tile<double
             const int t = *tick;
             __syncthreads();
             if (t != members - 1) return;   // the whole block leaves
-            if (team == 0) {
-                // four nodes in flight at a time (the registers of eight
-                // would spill at three waves per SIMD)
+            // node q of the group into slot q: the block's own node from
+            // team 0's registers, the others loaded two per team, every load
+            // in flight at once
+            if (team == 0) slot_store<G, double>(slots + (idx - first) * G::SLOT, Q, L);
+            Tile<double> X[2];
 #pragma unroll
-                for (int h = 0; h < kFanIn; h += kFanIn / 2) {
-                    Tile<double> X[kFanIn / 2];
+            for (int h = 0; h < 2; ++h) {
+                const int q = team + h * NT;
+                if (q < members && first + q != idx) X[h] = node_load_coherent<G>(p.nodes + (off + first + q) * NN, L);
+            }
 #pragma unroll
-                    for (int q = 0; q < kFanIn / 2; ++q)
-                        X[q] = (h + q < members && first + h + q != idx)
-                                   ? node_load_coherent<G>(p.nodes + (off + first + h + q) * NN, L)
-                                   : Q;
-#pragma unroll
-                    for (int q = 0; q < kFanIn / 2; ++q)
-                        if (h + q < members) slot_store<G, double>(slots + (h + q) * G::SLOT, X[q], L);
-                }
+            for (int h = 0; h < 2; ++h) {
+                const int q = team + h * NT;
+                if (q < members && first + q != idx) slot_store<G, double>(slots + q * G::SLOT, X[h], L);
             }
             __syncthreads();
 #pragma unroll

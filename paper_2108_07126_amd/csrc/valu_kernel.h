@@ -732,7 +732,7 @@ propagate_valu(PropParams p) {
     using S = Stage<T, D>;
     // the block's copy of the basis (after the four staging buffers)
     double* lbasis = reinterpret_cast<double*>(stage_lds + 4 * S::BUF);
-    for (int q = threadIdx.x; q < p.M * D * D * 2; q += blockDim.x) lbasis[q] = p.basis[q];
+    block_copy_to_lds(lbasis, p.basis, p.M * D * D * 2);
     __syncthreads();
     char* sbuf = stage_lds + wib * S::BUF;
     char* srow = sbuf + lane * S::STRIDE;
