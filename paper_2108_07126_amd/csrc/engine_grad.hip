@@ -493,6 +493,9 @@ backward_pipe(GradParams gp) {
     const int wave = wave_uniform((int)(threadIdx.x >> 6));
     const int role = wave / UPB;
     const int ub = wave % UPB;   // the unit within the block
+    // the derivative side is the longer of the two per slice: its waves go
+    // first in their SIMD's issue (78 -> 75 us per evaluation at N = 4096)
+    if (role == 1) __builtin_amdgcn_s_setprio(2);
     double* s0 = slots + wave * 2 * G::SLOT;
     double* s1 = s0 + G::SLOT;
     if constexpr (BL) {
