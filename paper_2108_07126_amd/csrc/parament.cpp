@@ -431,7 +431,7 @@ int tune_class(int D) {
 // chain per resident wave (two per SIMD): in FP32 at 2^26 slices 1.14 ms
 // against 1.38 ms with the tuned 1024 chains (FP64 is tuned to the same count;
 // for d=4 the tuned counts measured as fast or faster).
-int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool keep_nodes, bool per_slice) {
+int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool per_slice) {
     int64_t target = (int64_t)e.resident_chains;
     const int tc = tune_class(e.D);
     const bool tuned = !(per_slice && e.kind == pm::ENGINE_VALU && e.D == 2);
@@ -453,11 +453,10 @@ int64_t auto_chunk(const pm::EngineInfo& e, int64_t N, int precision, bool keep_
 // Chain length of a propagation: the user's, else the automatic one; whole
 // units, and for the VALU engine at most 2^20 slices (its per-slice output
 // addresses a chain's slices with 32-bit offsets).
-int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, bool keep_nodes = false,
-                        bool per_slice = false) {
+int64_t effective_chunk(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, bool per_slice = false) {
     if (ctx->call_chunk > 0) return ctx->call_chunk;
     int64_t c = ctx->chunk_override > 0 ? ctx->chunk_override
-                                        : auto_chunk(e, N, ctx->precision, keep_nodes, per_slice);
+                                        : auto_chunk(e, N, ctx->precision, per_slice);
     c = ((c + e.chunk_unit - 1) / e.chunk_unit) * e.chunk_unit;
     if (e.kind == pm::ENGINE_VALU && c > (int64_t(1) << 20)) c = int64_t(1) << 20;
     // CF4: a chain starts at a slice boundary (an even exponential index)
@@ -530,8 +529,7 @@ size_t call_bytes(const pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, int64_t
 // does not fit, or when the length fixed by pm_set_chunk does not.
 pm_status plan_call(pm_ctx* ctx, const pm::EngineInfo& e, int64_t N, int kind, bool per_slice, size_t extra,
                     int64_t* chunk_out, size_t* bytes_out) {
-    const bool keep = kind != PM_WORK_PROPAGATE;
-    int64_t c = effective_chunk(ctx, e, N, keep, per_slice);
+    int64_t c = effective_chunk(ctx, e, N, per_slice);
     size_t b = call_bytes(ctx, e, N, c, kind) + extra;
     const size_t lim = (size_t)ctx->ws_limit;
     if (ctx->ws_limit > 0 && b > lim) {
@@ -623,7 +621,7 @@ pm_status prepare(pm_ctx* ctx, const pm::EngineInfo& e, bool keep_nodes, const d
                   int64_t n_samples, double dt, double* d_U, void* d_slices, pm::PropParams* out,
                   const FixedWorkspace* fixed = nullptr) {
     const int64_t N = n_exps_of(ctx->order, n_samples);
-    const int64_t chunk = effective_chunk(ctx, e, N, keep_nodes, d_slices != nullptr);
+    const int64_t chunk = effective_chunk(ctx, e, N, d_slices != nullptr);
     const int64_t chains = (N + chunk - 1) / chunk;
     const int64_t leaves = (chains + e.chains_per_leaf - 1) / e.chains_per_leaf;
     const size_t node_bytes = (size_t)e.D * e.D * 16;
