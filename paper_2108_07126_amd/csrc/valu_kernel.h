@@ -670,12 +670,16 @@ __device__ __forceinline__ void stage_phased(char* row, const Mat<D, T>& U, doub
 // slice first + l * run.  Buffer stores with the range limited to the
 // slices that exist: pieces past the end are dropped by the hardware range
 // check, so the stores need no branches (and the compiler's wait counts stay
-// exact, letting the stores overlap the next slices' arithmetic).  D = 4
-// marks them non-temporal (measured 5 % faster there, 12 % slower at D = 2).
+// exact, letting the stores overlap the next slices' arithmetic).  D = 4 and
+// the FP64 D = 2 kernel mark them non-temporal: at D = 4 measured 5 % faster;
+// at D = 2 in FP64 the same time, but the output stream no longer evicts the
+// sample lines that lanes are still reading (HBM reads 1.61 -> 0.62 GB per
+// launch of 2^26 slices, the samples being 0.54 GB).
 template <typename T, int D>
 __device__ __forceinline__ void flush_stage(const PropParams& p, const char* buf, int64_t first, int64_t run,
                                             int lane) {
     using S = Stage<T, D>;
+    constexpr bool kNT = D == 4 || std::is_same<T, double>::value;
     const int64_t avail = p.n_slices - first;
     const int64_t span = 64 * run;
     const unsigned nrec = (unsigned)((avail < span ? (avail > 0 ? avail : 0) : span) * S::SB);
@@ -686,7 +690,7 @@ __device__ __forceinline__ void flush_stage(const PropParams& p, const char* buf
         const int piece = q * 64 + lane;
         const int seg = piece / S::PIECES, off = piece % S::PIECES;
         const v4u v = *reinterpret_cast<const v4u*>(buf + seg * S::STRIDE + off * 16);
-        __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)(seg * run * S::SB + off * 16), 0, D == 4 ? 2 : 0);
+        __builtin_amdgcn_raw_buffer_store_b128(v, rs, (int)(seg * run * S::SB + off * 16), 0, kNT ? 2 : 0);
     }
 }
 
