@@ -19,7 +19,7 @@ U = exp(-i H t), Computational approach section):
     The commutator sign is the one that makes U = exp(-i G) the 4th-order
     step for the standard product order (later slices on the left); the
     paper prints the opposite sign, which gives 4th order only in the
-    transposed, reversed-order view (reading recorded in the design doc).
+    transposed, reversed-order view (our reading of that sign).
     The commutator is formed from the assembled A1, A3, never through
     effective control Hamiltonians.
   - commutator-free 4th order (the alternative the Magnus integrators
