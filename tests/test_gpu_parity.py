@@ -204,6 +204,11 @@ def test_state_machine_and_errors(pm):
             ctx.equiprop(np.zeros((1, 5)), -0.1)
         with pytest.raises(pm.ParamentError):
             ctx.equiprop(np.full((1, 5), np.nan), 0.1)
+        for bad in (-2, 101):
+            with pytest.raises(pm.ParamentError) as e:
+                ctx.set_chain_skew(bad)
+            assert e.value.name == "PM_E_INVALID_ARG"
+        ctx.set_chain_skew(-1)
         # still usable
         U = ctx.equiprop(np.zeros((1, 5)), 0.1)
         assert orc.relative_frobenius(U, scipy.linalg.expm(-1j * synth.PAULI_Z * 0.2)) <= TOL64
