@@ -541,7 +541,7 @@ def main():
     ap.add_argument("--skip-batch", action="store_true")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU only: this build has no multi-GPU path "
+        print("bench.py measures one GPU only: the library has no multi-GPU path "
               "(the time axis would shard across GPUs with one gather of block products).",
               file=sys.stderr)
         sys.exit(2)
