@@ -327,8 +327,11 @@ __device__ __forceinline__ WeightRecipe m6_recipe(const PropParams& p, int lane)
     WeightRecipe r;
     const int q = lane >> 4, m = lane & 15;
     r.xb = q;
-    r.xa = m >= 1 ? (int64_t)(m - 1) * p.n_samples : 0;
     r.kind = (q > 2 || m >= p.M) ? 5 : (m == 0 ? 0 : 7);
+    // control m - 1's row for the lanes that weight a control (m <= K);
+    // every other lane still loads (its weight is zero), from row 0, so no
+    // lane reads past the K rows of samples
+    r.xa = r.kind == 7 ? (int64_t)(m - 1) * p.n_samples : 0;
     return r;
 }
 
