@@ -400,7 +400,8 @@ pm_status pm_set_expm_method(pm_ctx *ctx, int method);
  * so leaves <= chains).  The reduction performs chains - 1 products after the
  * chains.  Without a pm_set_chunk override, a propagation with per-slice
  * output on dimensions 1 and 2 uses one chain per resident wave instead of the
- * tuned count. */
+ * tuned count.  *chunk is the length before the uneven split of
+ * pm_set_chain_skew (which keeps the number of chains and leaves). */
 pm_status pm_launch_shape(pm_ctx *ctx, int64_t n_samples, int64_t *chunk, int64_t *chains,
                           int64_t *leaves);
 
