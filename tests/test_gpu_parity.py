@@ -287,7 +287,8 @@ def assoc_bound(n):
     return 64 * math.sqrt(n) * 2.0 ** -53
 
 
-@pytest.mark.parametrize("case", ["fp64_order4", "fp32_3m_order2", "fp64_cf4", "fp64_pairs_d8", "fp64_magnus6"])
+@pytest.mark.parametrize("case", ["fp64_order4", "fp32_3m_order2", "fp64_cf4", "fp64_pairs_d8", "fp64_magnus6",
+                                  "fp64_chebyshev"])
 def test_uneven_chains(pm, case):
     """A 16-wide-tile launch of exactly two blocks of four chains per compute
     unit gives the first-dispatched blocks' chains more slices
@@ -300,7 +301,7 @@ def test_uneven_chains(pm, case):
     prec = FP32_3M if case == "fp32_3m_order2" else 0
     d = 8 if case == "fp64_pairs_d8" else 16
     order = {"fp64_order4": 4, "fp32_3m_order2": 2, "fp64_cf4": orc.CF4, "fp64_pairs_d8": 2,
-             "fp64_magnus6": orc.M6}[case]
+             "fp64_magnus6": orc.M6, "fp64_chebyshev": 4}[case]
     n = chains * chunk // (2 if order == orc.CF4 else 1)   # CF4: two exponentials per slice
     w = synth.random_system(d, 3, n_slices=n, h=0.02, order=order, tag=77)
     slices = order not in (orc.CF4, orc.M6)
@@ -309,6 +310,8 @@ def test_uneven_chains(pm, case):
         say(f"[case] uneven chains {case} d={d} N={n} chunk={chunk} skew={skew}")
         with pm.Context(0, prec) as ctx:
             ctx.set_hamiltonian(w.H0, w.Hk, order)
+            if case == "fp64_chebyshev":
+                ctx.set_expm_method(pm.PM_EXPM_CHEBYSHEV)
             ctx.set_chunk(chunk)
             ctx.set_chain_skew(skew)
             assert ctx.launch_shape(w.n_samples)[1:] == (chains, chains // 4)
