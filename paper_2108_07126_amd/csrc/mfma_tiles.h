@@ -959,9 +959,24 @@ __device__ void cheb_parts(const Tile<double>& Gt, int m, double theta, const do
         }
         axpy(C, ec[1], Y);
         if (qs >= 1) axpy(Sp, eb[1], Y);
+        if constexpr (G::TW > 1) {
+            // multi-wave teams: Y, the same left factor of every step, is
+            // staged once and read from its slot; the recurrence then holds
+            // two terms of T and no copy of Y in registers
+            team_sync<G>();
+            slot_store<G, double>(s0, Y, L);
+        }
         Tile<double> Tm = ident<double>(L), Tc = Y;
         for (int i = 2; i <= qc; ++i) {
-            Tile<double> Tn = herm_mul<G>(Y, Tc, L, s0, s1);
+            Tile<double> Tn;
+            if constexpr (G::TW > 1) {
+                team_sync<G>();
+                slot_store<G, double>(s1, Tc, L);
+                team_sync<G>();
+                Tn = slot_mul<G, double>(s0, s1, L);
+            } else {
+                Tn = herm_mul<G>(Y, Tc, L, s0, s1);
+            }
 #pragma unroll
             for (int r = 0; r < 4; ++r) {
                 Tn.re[r] = fma(2.0, Tn.re[r], -Tm.re[r]);
