@@ -363,3 +363,24 @@ def test_uneven_chains_small_dims(pm, d):
         assert orc.relative_frobenius(U, out[0][0]) <= assoc_bound(n), skew
         assert orc.relative_frobenius(U, Uo) <= TOL64, skew
     assert np.max(np.abs(out[-1][1] - slo)) <= 1e-13
+
+
+@pytest.mark.parametrize("d", [1, 2, 3, 4])
+def test_small_dims_sample_block_edges(pm, d):
+    """Order 2 on the small-dimension engine where its sample blocks meet
+    their edges: no controls (nothing is loaded), a single slice (one sample
+    per control, read where it is used), and lengths that end inside a
+    block, on the last sample of a 16-byte piece (N = 3, 17, 1001) and on a
+    whole piece (N = 2); every slice and U(T) against the oracle, in FP64
+    and FP32."""
+    for K in (0, 1, 2):
+        for n in (1, 2, 3, 17, 1001):
+            w = synth.random_system(d, K, n_slices=n, h=0.05, order=2, tag=300 + n)
+            Uo, slo = orc.propagate(w.H0, w.Hk, w.samples, w.h, 2, return_slices=True)
+            U, sl = run(pm, w, slices=True)
+            assert orc.relative_frobenius(U, Uo) <= TOL64, (K, n)
+            assert np.max(np.abs(sl - slo)) <= 1e-13, (K, n)
+            U32v, sl32 = run(pm, w, precision=pm.PM_FP32, slices=True)
+            sq = max_squarings(pm, w, pm.PM_FP32, shift=True)
+            assert orc.relative_frobenius(U32v, Uo) <= tol32(n, d, sq), (K, n)
+            assert np.max(np.abs(sl32 - slo)) <= tol_slice(FP32, d, sq), (K, n)
