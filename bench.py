@@ -53,7 +53,7 @@ PEAK = {"fp64": PEAK_FP64_TFLOPS, "fp32": PEAK_FP32_TFLOPS, "fp32_3m": PEAK_FP32
 TRAFFIC_SOURCES = ["engine_mfma.hip", "mfma_kernel.h", "mfma_tiles.h", "mfma_tree.h", "engine_common.h", "pm_internal.h"]
 TRAFFIC_PROFILE = "profiles/propagate_d16_random_qudit_traffic.md"
 LEGS = ["precisions", "slices", "d64", "small", "chebyshev", "cf4", "trajectory", "grad", "grape", "batch", "cpu",
-        "fixed_error"]
+        "fixed_error", "magnus6"]
 
 
 def taylor_products(m: int) -> int:
@@ -519,6 +519,62 @@ def leg_fixed_error(pm, torch, dev, modes):
     return res
 
 
+def leg_magnus6(pm, torch, dev):
+    """The sixth-order Magnus scheme (three Gauss-Legendre samples per slice)
+    against the fourth-order step on the random qudit (d = 16, 3 controls)
+    over its fixed span T = 2^17 * 1e-3, in FP64.  N = 2^n slices of width
+    T / N; the error of U(T) is taken against the oracle's sixth-order U(T)
+    at N = 2^17, stored by tests/golden/make_full_size.py.  Targets are met
+    only at N <= 2^15, where the reference's own discretisation error is at
+    most 1/4^6 of the sixth-order run's.  For each target: the smallest N
+    reaching it with either scheme, its kernel time (HIP events on the
+    launch stream), and the fourth- over sixth-order time at equal accuracy.
+    At N = 2^17 both schemes' cost per slice, and the sixth-order run's
+    difference from the oracle at the same N (a full-size parity figure)."""
+    import synth
+    if not os.path.exists(GOLDEN):
+        return {"skipped": "no stored oracle reference"}
+    with np.load(GOLDEN) as z:
+        if "random_qudit_m6" not in z.files:
+            return {"skipped": "no stored oracle reference"}
+        ref = z["random_qudit_m6"]
+    full = 2 ** 17
+    T = full * 1e-3
+    targets = (1e-4, 1e-6, 1e-8)
+    orders = (("magnus4", 4), ("magnus6", pm.PM_ORDER_MAGNUS6))
+    res = {"workload": "random_qudit_d16_K3, span T = 131.072", "span_T": T, "targets": list(targets),
+           "reference": f"oracle U(T), sixth order, N = {full}; targets searched at N <= {full // 4}"}
+    curves = {}
+    for name, order in orders:
+        w0 = synth.random_qudit(n_slices=2 ** 9, h=T / 2 ** 9, order=order)
+        ctx = pm.Context(0, pm.PM_FP64)
+        ctx.set_hamiltonian(w0.H0, w0.Hk, order)
+        cur = {}
+        for n in list(range(9, 16)) + [17]:
+            nn = 2 ** n
+            wn = synth.random_qudit(n_slices=nn, h=T / nn, order=order)
+            sd = torch.from_numpy(wn.samples).to(dev)
+            Ud = torch.zeros((wn.dim, wn.dim), dtype=torch.complex128, device=dev)
+            _, kms = time_launches(lambda: ctx.equiprop_dev(sd, wn.h, Ud), 5, 2)
+            cur[nn] = {"err": rel_frobenius(Ud.cpu().numpy(), ref), "kernel_ms": kms}
+        ctx.close()
+        curves[name] = cur
+        res[name] = {str(k): v for k, v in cur.items()}
+    summ = {}
+    for eps in targets:
+        row = {}
+        for name, _ in orders:
+            ok = [k for k, v in curves[name].items() if k <= full // 4 and v["err"] <= eps]
+            row[name] = {"n_slices": min(ok), "kernel_ms": curves[name][min(ok)]["kernel_ms"]} if ok else None
+        if row["magnus4"] and row["magnus6"]:
+            row["magnus4_over_magnus6_kernel_time"] = row["magnus4"]["kernel_ms"] / row["magnus6"]["kernel_ms"]
+        summ[f"eps_{eps:.0e}"] = row
+    res["summary"] = summ
+    res["ns_per_slice_at_2^17"] = {name: curves[name][full]["kernel_ms"] / full * 1e6 for name, _ in orders}
+    res["magnus6_rel_err_vs_oracle_at_2^17"] = curves["magnus6"][full]["err"]
+    return res
+
+
 def leg_copy(torch, dev, out):
     """A plain device copy of 1 GiB (reads 1 GiB, writes 1 GiB): the
     calibration kernel for the FETCH_SIZE / WRITE_SIZE counters."""
@@ -732,6 +788,8 @@ def main():
 
     if "fixed_error" in legs:
         out["fixed_error"] = leg_fixed_error(pm, torch, dev, modes)
+    if "magnus6" in legs:
+        out["magnus6"] = leg_magnus6(pm, torch, dev)
 
     if "chebyshev" in out:
         for row in out["chebyshev"].values():

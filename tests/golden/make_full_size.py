@@ -9,6 +9,9 @@ nothing comes from the library.
 
 Contents:
   random_qudit      U(T) of the d = 16 random qudit at N = 2^17 (order 4)
+  random_qudit_m6   U(T) of the same system with the sixth-order scheme at
+                    N = 2^17 (its three Gauss-Legendre samples per slice; the
+                    reference of the sixth- against fourth-order comparison)
   precision_sweep   U(T) of the d = 64 precision sweep at N = 2^16 (order 2)
   precision_sweep_fine
                     U(T) of the same system over the same span at N = 2^19
@@ -70,6 +73,8 @@ def _job(key):
     t0 = time.time()
     if key == "random_qudit":
         w = synth.random_qudit()
+    elif key == "random_qudit_m6":
+        w = synth.random_qudit(order=orc.M6)
     elif key == "precision_sweep":
         w = synth.precision_sweep()
     else:
@@ -108,9 +113,9 @@ def main() -> None:
     insts = synth.batched_instances(512)
     sel = batch_selection(insts)
     # longest jobs first so the pool drains evenly
-    jobs = ["precision_sweep", "random_qudit"] + [str(i) for i in sel]
+    jobs = ["precision_sweep", "random_qudit", "random_qudit_m6"] + [str(i) for i in sel]
     jobs.sort(key=lambda k: -(2 ** 16 * 64 ** 3 if k == "precision_sweep" else
-                              2 ** 17 * 16 ** 3 if k == "random_qudit" else
+                              2 ** 17 * 16 ** 3 if k.startswith("random_qudit") else
                               insts[int(k)].n_slices * insts[int(k)].dim ** 3))
     res = {}
     with ProcessPoolExecutor(max_workers=min(8, os.cpu_count() or 1)) as ex:
@@ -126,7 +131,8 @@ def main() -> None:
     for i in sel:
         flat.append(res[str(i)].reshape(-1))
         offs.append(offs[-1] + flat[-1].size)
-    np.savez_compressed(OUT, random_qudit=res["random_qudit"], precision_sweep=res["precision_sweep"],
+    np.savez_compressed(OUT, random_qudit=res["random_qudit"], random_qudit_m6=res["random_qudit_m6"],
+                        precision_sweep=res["precision_sweep"],
                         precision_sweep_fine=res["precision_sweep_fine"],
                         batch_index=np.array(sel, np.int64), batch_offset=np.array(offs, np.int64),
                         batch_U=np.concatenate(flat))

@@ -7,6 +7,7 @@ are regenerated here from the same seeds.
 
 * the random qudit (d = 16, N = 2^17, order 4) in every precision, with
   per-slice output sampled against the oracle's slice exponentials;
+* the same system with the sixth-order scheme (FP64), likewise;
 * the precision sweep (d = 64, N = 2^16, order 2) in every precision;
 * the 512-instance batch at full N: FP64 and FP32-3M batches against the
   stored U(T) of every instance of dimension <= 16 and of the longest
@@ -78,6 +79,26 @@ def test_random_qudit_full_size(pm, golden, prec):
     sbound = 1e-13 if prec == 0 else tol_slice(prec, w.dim)
     say(f"  sampled slices max-abs err {worst:.3e} (bound {sbound:.3e})")
     assert worst <= sbound
+
+
+def test_random_qudit_magnus6_full_size(pm, golden):
+    """d = 16, N = 2^17 with the sixth-order scheme (three Gauss-Legendre
+    samples per slice, FP64): U(T) against the stored oracle product, and 64
+    sampled slices against the oracle's sixth-order slice exponentials."""
+    w = synth.random_qudit(order=orc.M6)
+    say("[case] random qudit full size, sixth order")
+    U, sl = propagate(pm, w, 0, slices=True)
+    err = orc.relative_frobenius(U, golden["random_qudit_m6"])
+    say(f"  U(T) rel err {err:.3e} (bound {TOL64:.1e})")
+    assert err <= TOL64
+    rng = np.random.default_rng(2)
+    js = np.sort(rng.choice(w.n_slices, 64, replace=False))
+    worst = 0.0
+    for j in js:
+        G = orc.slice_exponents(w.H0, w.Hk, w.samples, w.h, orc.M6, j, j + 1)
+        worst = max(worst, float(np.max(np.abs(sl[j] - orc.expm_minus_i(G)[0]))))
+    say(f"  sampled slices max-abs err {worst:.3e} (bound 1e-13)")
+    assert worst <= 1e-13
 
 
 @pytest.mark.parametrize("prec", [0, 1, 2, 3])

@@ -200,3 +200,18 @@ def test_planted_equispaced_samples_are_caught():
         c = np.stack([np.cos(t), np.sin(t)])
         errs.append(orc.relative_frobenius(orc.propagate(w.H0, w.Hk, c, w.h, M6), circular_exact()))
     assert abs(slope(ns, errs) - 6.0) > 0.5
+
+
+def test_stored_full_size_sixth_order_reference():
+    """The stored sixth-order U(T) of the d = 16 random qudit (N = 2^17,
+    written by tests/golden/make_full_size.py with the oracle) is unitary and
+    agrees with the stored fourth-order U(T) of the same system over the same
+    span within the fourth-order scheme's own error there: that scheme needs
+    N = 2^15 for 1e-6, so at 2^17 (h / 4) its error is below 1e-6 / 4^4
+    = 3.9e-9; bound 1e-8."""
+    import os
+    path = os.path.join(os.path.dirname(os.path.abspath(__file__)), "golden", "full_size_oracle.npz")
+    with np.load(path) as z:
+        U6, U4 = z["random_qudit_m6"], z["random_qudit"]
+    assert np.max(np.abs(U6.conj().T @ U6 - np.eye(16))) <= 1e-11
+    assert orc.relative_frobenius(U6, U4) <= 1e-8
